@@ -1,0 +1,253 @@
+"""FP64 CPU oracle of the adaptive PBF step (ctypes wrapper of oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product library
+never does.  It shares no code with the HIP path; both read their inputs
+from the ``scenes`` generator only.
+
+See oracle.c for the equations followed and the readings taken where the
+paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "oracle.c"
+_LIB_PATH = _HERE / "liboracle.so"
+
+ORC_OK, ORC_ERR_ARG, ORC_ERR_MEM = 0, -1, -3
+
+
+def build(force: bool = True) -> Path:
+    """Compile oracle.c with gcc (OpenMP, strict FP: no contraction)."""
+    if force or not _LIB_PATH.exists() or _LIB_PATH.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB_PATH.with_suffix(".so.tmp")
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", str(_SRC), "-o", str(tmp), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_min", ctypes.c_int32), ("n_max", ctypes.c_int32),
+                ("dims", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("mass", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double),
+                ("g", ctypes.c_double * 3)]
+
+
+class Lod(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("levels", ctypes.POINTER(ctypes.c_int32)),
+                ("camera", ctypes.c_double * 3), ("d_near", ctypes.c_double),
+                ("d_far", ctypes.c_double)]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("levels", ctypes.POINTER(ctypes.c_int32)),
+                ("keys", ctypes.POINTER(ctypes.c_uint32)),
+                ("perm", ctypes.POINTER(ctypes.c_int32)),
+                ("nbr_count", ctypes.POINTER(ctypes.c_int32)),
+                ("nbr_ids", ctypes.POINTER(ctypes.c_int32)),
+                ("nbr_cap", ctypes.c_int64), ("nbr_total", ctypes.c_int64),
+                ("xs_iter", ctypes.POINTER(ctypes.c_double)),
+                ("lambda_iter", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            build(force=True)
+        L = ctypes.CDLL(str(_LIB_PATH))
+        L.orc_poly6.restype = ctypes.c_double
+        L.orc_poly6.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_spiky_grad.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.orc_apbf_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Trace)]
+        L.orc_pbf_step.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+        L.orc_density.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_levels.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod), ctypes.c_void_p,
+                                 ctypes.c_void_p]
+        L.orc_cell_keys.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_counting_sort.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
+        L.orc_get_threads.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def set_threads(t: int) -> None:
+    lib().orc_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
+def poly6(r2: float, h: float) -> float:
+    return float(lib().orc_poly6(float(r2), float(h)))
+
+
+def spiky_grad(d, h: float) -> np.ndarray:
+    d = np.ascontiguousarray(d, np.float64).reshape(3)
+    out = np.zeros(3, np.float64)
+    lib().orc_spiky_grad(_ptr(d, ctypes.c_double), float(h), _ptr(out, ctypes.c_double))
+    return out
+
+
+def params(scene, n=None, n_min=None, n_max=None) -> Params:
+    """Widen a scene's float32 parameters to the oracle's float64 struct."""
+    p = Params()
+    p.n = scene.n if n is None else int(n)
+    p.n_min = scene.n_min if n_min is None else int(n_min)
+    p.n_max = scene.n_max if n_max is None else int(n_max)
+    for d in range(3):
+        p.dims[d] = int(scene.dims[d])
+        p.lo[d] = float(scene.lo[d])
+        p.hi[d] = float(scene.hi[d])
+        p.g[d] = float(scene.gravity[d])
+    p.h, p.rho0, p.mass = float(scene.h), float(scene.rho0), float(scene.mass)
+    p.eps, p.dt = float(scene.eps), float(scene.dt)
+    return p
+
+
+class _LodHolder:
+    def __init__(self, scene, mode=None, levels=None):
+        self.lod = Lod()
+        self.lod.mode = scene.lod_mode if mode is None else int(mode)
+        lv = scene.levels if levels is None else levels
+        self.levels = None
+        if self.lod.mode == 1:
+            self.levels = np.ascontiguousarray(lv, np.int32)
+            self.lod.levels = _ptr(self.levels, ctypes.c_int32)
+        for d in range(3):
+            self.lod.camera[d] = float(scene.camera[d])
+        self.lod.d_near, self.lod.d_far = float(scene.d_near), float(scene.d_far)
+
+
+def levels(scene, x) -> np.ndarray:
+    p = params(scene)
+    hold = _LodHolder(scene)
+    x = np.ascontiguousarray(x, np.float64)
+    out = np.zeros(scene.n, np.int32)
+    rc = lib().orc_levels(ctypes.byref(p), ctypes.byref(hold.lod), x.ctypes.data, out.ctypes.data)
+    if rc != ORC_OK:
+        raise ValueError(f"orc_levels failed ({rc})")
+    return out
+
+
+def apbf_step(scene, x, v, trace=False, mode=None, levels=None, n_min=None, n_max=None):
+    """Advance float64 (n, 3) arrays x, v by one APBF step (copies are made).
+
+    Returns (x, v, info); with trace=True info holds levels, keys, perm,
+    neighbour CSR (count, ids), x* before/after every iteration and lambda
+    after every lambda pass."""
+    p = params(scene, n_min=n_min, n_max=n_max)
+    hold = _LodHolder(scene, mode, levels)
+    x = np.array(x, np.float64, order="C").reshape(-1, 3)
+    v = np.array(v, np.float64, order="C").reshape(-1, 3)
+    n, K = p.n, p.n_max
+    info = {}
+    tr = None
+    if trace:
+        info = {
+            "levels": np.zeros(n, np.int32), "keys": np.zeros(n, np.uint32),
+            "perm": np.zeros(n, np.int32), "nbr_count": np.zeros(n, np.int32),
+            "xs_iter": np.zeros((K + 1, n, 3), np.float64),
+            "lambda_iter": np.zeros((K, n), np.float64),
+        }
+        tr = Trace()
+        tr.levels = _ptr(info["levels"], ctypes.c_int32)
+        tr.keys = _ptr(info["keys"], ctypes.c_uint32)
+        tr.perm = _ptr(info["perm"], ctypes.c_int32)
+        tr.nbr_count = _ptr(info["nbr_count"], ctypes.c_int32)
+        tr.xs_iter = _ptr(info["xs_iter"], ctypes.c_double)
+        tr.lambda_iter = _ptr(info["lambda_iter"], ctypes.c_double)
+        # first call sizes the neighbour list, second call fills it
+        x0, v0 = x.copy(), v.copy()
+        tr.nbr_cap = 0
+        rc = lib().orc_apbf_step(ctypes.byref(p), ctypes.byref(hold.lod), x0.ctypes.data,
+                                 v0.ctypes.data, ctypes.byref(tr))
+        if rc != ORC_OK:
+            raise ValueError(f"orc_apbf_step failed ({rc})")
+        ids = np.zeros(max(int(tr.nbr_total), 1), np.int32)
+        info["nbr_ids"] = ids[: int(tr.nbr_total)]
+        tr.nbr_ids = _ptr(ids, ctypes.c_int32)
+        tr.nbr_cap = ids.size
+    rc = lib().orc_apbf_step(ctypes.byref(p), ctypes.byref(hold.lod), x.ctypes.data,
+                             v.ctypes.data, ctypes.byref(tr) if tr is not None else None)
+    if rc != ORC_OK:
+        raise ValueError(f"orc_apbf_step failed ({rc})")
+    if trace:
+        off = np.zeros(n + 1, np.int64)
+        np.cumsum(info["nbr_count"], out=off[1:])
+        info["nbr_off"] = off
+    return x, v, info
+
+
+def pbf_step(scene, x, v, iters):
+    """Plain PBF step with a fixed iteration count (separate loop, no gating)."""
+    p = params(scene)
+    x = np.array(x, np.float64, order="C").reshape(-1, 3)
+    v = np.array(v, np.float64, order="C").reshape(-1, 3)
+    rc = lib().orc_pbf_step(ctypes.byref(p), int(iters), x.ctypes.data, v.ctypes.data)
+    if rc != ORC_OK:
+        raise ValueError(f"orc_pbf_step failed ({rc})")
+    return x, v
+
+
+def density(scene, x) -> np.ndarray:
+    p = params(scene)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    rho = np.zeros(p.n, np.float64)
+    rc = lib().orc_density(ctypes.byref(p), x.ctypes.data, rho.ctypes.data)
+    if rc != ORC_OK:
+        raise ValueError(f"orc_density failed ({rc})")
+    return rho
+
+
+def cell_keys(scene, xs) -> np.ndarray:
+    p = params(scene, n=len(xs))
+    xs = np.ascontiguousarray(xs, np.float64).reshape(-1, 3)
+    out = np.zeros(p.n, np.uint32)
+    lib().orc_cell_keys(ctypes.byref(p), xs.ctypes.data, out.ctypes.data)
+    return out
+
+
+def counting_sort(scene, keys) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, np.uint32)
+    p = params(scene, n=keys.size)
+    G = int(np.prod(scene.dims.astype(np.int64)))
+    perm = np.zeros(keys.size, np.int32)
+    start = np.zeros(G + 1, np.int64)
+    rc = lib().orc_counting_sort(ctypes.byref(p), keys.ctypes.data, perm.ctypes.data,
+                                 start.ctypes.data)
+    if rc != ORC_OK:
+        raise ValueError("orc_counting_sort failed")
+    return perm
+
+
+def run(scene, steps=None, x=None, v=None, mode=None, levels=None):
+    """Run the oracle for a number of steps from the scene's initial state."""
+    x = scene.x0.astype(np.float64) if x is None else x
+    v = scene.v0.astype(np.float64) if v is None else v
+    for _ in range(scene.steps if steps is None else steps):
+        x, v, _ = apbf_step(scene, x, v, mode=mode, levels=levels)
+    return x, v

@@ -1,0 +1,522 @@
+/*
+ * FP64 CPU oracle of one adaptive position-based-fluids (APBF) time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * path (the HIP library) never calls it and shares no code with it.
+ *
+ * Plain, slow, obviously-correct loops in double precision, following the
+ * paper step by step:
+ *   - constraint projection with a scaling factor (Eqs. 1-4),
+ *   - density constraint and SPH density estimate (Eqs. 5-6),
+ *   - position correction (Eq. 7),
+ *   - levels, active predicate, active set and finished set (Eqs. 8-11),
+ *   - the simulation loop of Section 5 (Fig. 7): apply forces and predict,
+ *     find neighbours, then per solver iteration compute lambda, compute the
+ *     correction with contact response, and update, for active particles
+ *     only; finally update velocity and position of every particle,
+ *   - neighbour discovery by counting sort of uniform-grid cell keys
+ *     (Section 6).
+ *
+ * Readings where the paper is silent (they are the same in the HIP path):
+ *   - W is the poly6 kernel, grad W the spiky-kernel gradient (Mueller et
+ *     al. 2003); the density includes the particle itself.
+ *   - Uniform mass m: Eq. 7 carries the weight w_i = 1/m of Eq. 3 and the
+ *     m_j of Eq. 6, so Delta p_i = (1/rho0) sum_j (lambda_i + lambda_j) grad W.
+ *   - Eq. 4's denominator gets a relaxation eps, lambda = -C / (S + eps).
+ *   - Neighbour sets are found once per step from the predicted positions,
+ *     with the strict test |x_i - x_j|^2 < h^2, and kept for all iterations.
+ *   - A finished particle keeps its position and its last lambda; active
+ *     particles use that lambda in their corrections (Fig. 5).
+ *   - Contacts are the box walls: positions are clamped to [lo, hi] after
+ *     prediction and after each update.  No pre-stabilisation iterations.
+ *   - Iterations k = 0 .. n_max-1 (the paper's l = k + 1); particle i is
+ *     active while k < N_i.
+ *   - Grid cells have edge h from lo, keys are x-fastest, coordinates are
+ *     clamped into the grid; ties in the counting sort keep particle-ID
+ *     order (a stable counting sort of the particles listed by ID).
+ *   - Distance-to-camera levels: t = clamp((d - d_near)/(d_far - d_near)),
+ *     N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max).
+ * Neighbour sums run in ascending particle-ID order, so results do not
+ * depend on any storage order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    int32_t n, n_min, n_max;
+    int32_t dims[3];
+    double lo[3], hi[3];
+    double h, rho0, mass, eps, dt;
+    double g[3];
+} orc_params;
+
+typedef struct {
+    int32_t mode;           /* 0 uniform (N_i = n_max), 1 explicit, 2 distance to camera */
+    const int32_t *levels;  /* explicit: n levels in particle-ID order */
+    double camera[3];
+    double d_near, d_far;
+} orc_lod;
+
+typedef struct {
+    int32_t *levels;        /* [n]  N_i used this step */
+    uint32_t *keys;         /* [n]  cell key of the predicted position */
+    int32_t *perm;          /* [n]  sorted order as a list of particle IDs */
+    int32_t *nbr_count;     /* [n]  |N_i| */
+    int32_t *nbr_ids;       /* [nbr_cap] neighbour IDs, particle by particle, ascending */
+    int64_t nbr_cap;
+    int64_t nbr_total;      /* out: total entries (written even when nbr_ids is too small) */
+    double *xs_iter;        /* [(n_max+1)*n*3] x* before iteration 0 and after each */
+    double *lambda_iter;    /* [n_max*n] lambda after the lambda pass of each iteration */
+} orc_trace;
+
+enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_MEM = -3 };
+
+/* ------------------------------------------------------------------ */
+/* smoothing kernels                                                   */
+/* ------------------------------------------------------------------ */
+
+/* poly6: W(r) = 315 / (64 pi h^9) (h^2 - r^2)^3 for r < h, else 0. */
+double orc_poly6(double r2, double h)
+{
+    if (r2 >= h * h) return 0.0;
+    double t = h * h - r2;
+    return 315.0 / (64.0 * M_PI * pow(h, 9)) * t * t * t;
+}
+
+/* Gradient with respect to p_i of the spiky kernel 15/(pi h^6) (h - r)^3,
+ * evaluated at d = p_i - p_j:  -45/(pi h^6) (h - r)^2 d / r for 0 < r < h. */
+void orc_spiky_grad(const double d[3], double h, double out[3])
+{
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    out[0] = out[1] = out[2] = 0.0;
+    if (r <= 0.0 || r >= h) return;
+    double c = -45.0 / (M_PI * pow(h, 6)) * (h - r) * (h - r) / r;
+    out[0] = c * d[0];
+    out[1] = c * d[1];
+    out[2] = c * d[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* grid                                                                */
+/* ------------------------------------------------------------------ */
+
+static int64_t n_cells(const orc_params *p)
+{
+    return (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
+}
+
+static void cell_of(const orc_params *p, const double *x, int32_t c[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        double q = floor((x[d] - p->lo[d]) / p->h);
+        if (q < 0) q = 0;
+        if (q > p->dims[d] - 1) q = p->dims[d] - 1;
+        c[d] = (int32_t)q;
+    }
+}
+
+static uint32_t key_of(const orc_params *p, const int32_t c[3])
+{
+    return (uint32_t)(((int64_t)c[2] * p->dims[1] + c[1]) * p->dims[0] + c[0]);
+}
+
+void orc_cell_keys(const orc_params *p, const double *xs, uint32_t *keys)
+{
+    for (int32_t i = 0; i < p->n; ++i) {
+        int32_t c[3];
+        cell_of(p, xs + 3 * (int64_t)i, c);
+        keys[i] = key_of(p, c);
+    }
+}
+
+/* Counting sort of particle IDs by cell key (Section 6): histogram,
+ * exclusive prefix sum, then scatter in ID order, which keeps ties in ID
+ * order.  start[] has n_cells + 1 entries. */
+int orc_counting_sort(const orc_params *p, const uint32_t *keys, int32_t *perm,
+                      int64_t *start)
+{
+    int64_t G = n_cells(p);
+    int64_t *fill = (int64_t *)calloc((size_t)G + 1, sizeof(int64_t));
+    if (!fill) return ORC_ERR_MEM;
+    for (int64_t c = 0; c <= G; ++c) start[c] = 0;
+    for (int32_t i = 0; i < p->n; ++i) start[keys[i] + 1] += 1;
+    for (int64_t c = 0; c < G; ++c) start[c + 1] += start[c];
+    for (int32_t i = 0; i < p->n; ++i) {
+        uint32_t k = keys[i];
+        perm[start[k] + fill[k]] = i;
+        fill[k] += 1;
+    }
+    free(fill);
+    return ORC_OK;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Neighbour sets N_i = { j != i : |x_i - x_j|^2 < h^2 } by scanning the 27
+ * cells around the cell of x_i (Fig. 7, neighbour step); each set is sorted
+ * by ascending ID.  Returns CSR arrays (caller frees). */
+static int find_neighbours(const orc_params *p, const double *xs, const int32_t *perm,
+                           const int64_t *start, int64_t **off_out, int32_t **ids_out)
+{
+    const int32_t n = p->n;
+    const double h2 = p->h * p->h;
+    int64_t *off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!off) return ORC_ERR_MEM;
+
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t *ids = NULL;
+        if (pass == 1) {
+            for (int32_t i = 0; i < n; ++i) off[i + 1] += off[i];
+            ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(off[n] > 0 ? off[n] : 1));
+            if (!ids) { free(off); return ORC_ERR_MEM; }
+            *ids_out = ids;
+        }
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i) {
+            const double *xi = xs + 3 * (int64_t)i;
+            int32_t c[3];
+            cell_of(p, xi, c);
+            int64_t cnt = 0;
+            for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int32_t q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                if (q[0] < 0 || q[1] < 0 || q[2] < 0 || q[0] >= p->dims[0] ||
+                    q[1] >= p->dims[1] || q[2] >= p->dims[2])
+                    continue;
+                uint32_t k = key_of(p, q);
+                for (int64_t t = start[k]; t < start[k + 1]; ++t) {
+                    int32_t j = perm[t];
+                    if (j == i) continue;
+                    const double *xj = xs + 3 * (int64_t)j;
+                    double dxv = xi[0] - xj[0], dyv = xi[1] - xj[1], dzv = xi[2] - xj[2];
+                    if (dxv * dxv + dyv * dyv + dzv * dzv < h2) {
+                        if (pass == 1) ids[off[i] + cnt] = j;
+                        ++cnt;
+                    }
+                }
+            }
+            if (pass == 0) off[i + 1] = cnt;
+            else qsort(ids + off[i], (size_t)cnt, sizeof(int32_t), cmp_i32);
+        }
+    }
+    *off_out = off;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* per-particle solver terms                                           */
+/* ------------------------------------------------------------------ */
+
+/* lambda_i of Eq. 4 for the density constraint of Eq. 5 with the density
+ * estimate of Eq. 6 (self term included).  The gradient of C_i with respect
+ * to p_i is (m/rho0) sum_j grad W_ij and with respect to p_j it is
+ * -(m/rho0) grad W_ij; each is weighted by w = 1/m. */
+static double lambda_of(const orc_params *p, const double *xs, int32_t i,
+                        const int32_t *nb, int64_t cnt, double *rho_out)
+{
+    const double *xi = xs + 3 * (int64_t)i;
+    const double w = 1.0 / p->mass;
+    double rho = p->mass * orc_poly6(0.0, p->h);
+    double gi[3] = {0.0, 0.0, 0.0};
+    double sum_wj = 0.0;
+    for (int64_t q = 0; q < cnt; ++q) {
+        const double *xj = xs + 3 * (int64_t)nb[q];
+        double d[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+        rho += p->mass * orc_poly6(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], p->h);
+        double gw[3];
+        orc_spiky_grad(d, p->h, gw);
+        double gj[3] = {-p->mass / p->rho0 * gw[0], -p->mass / p->rho0 * gw[1],
+                        -p->mass / p->rho0 * gw[2]};
+        sum_wj += w * (gj[0] * gj[0] + gj[1] * gj[1] + gj[2] * gj[2]);
+        gi[0] += p->mass / p->rho0 * gw[0];
+        gi[1] += p->mass / p->rho0 * gw[1];
+        gi[2] += p->mass / p->rho0 * gw[2];
+    }
+    double C = rho / p->rho0 - 1.0;
+    double denom = w * (gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2]) + sum_wj;
+    if (rho_out) *rho_out = rho;
+    return -C / (denom + p->eps);
+}
+
+/* Delta p_i of Eq. 7 (uniform mass): (1/rho0) sum_j (lambda_i + lambda_j) grad W_ij. */
+static void delta_p_of(const orc_params *p, const double *xs, const double *lam, int32_t i,
+                       const int32_t *nb, int64_t cnt, double dp[3])
+{
+    const double *xi = xs + 3 * (int64_t)i;
+    dp[0] = dp[1] = dp[2] = 0.0;
+    for (int64_t q = 0; q < cnt; ++q) {
+        int32_t j = nb[q];
+        const double *xj = xs + 3 * (int64_t)j;
+        double d[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+        double gw[3];
+        orc_spiky_grad(d, p->h, gw);
+        double s = lam[i] + lam[j];
+        dp[0] += s * gw[0];
+        dp[1] += s * gw[1];
+        dp[2] += s * gw[2];
+    }
+    dp[0] /= p->rho0;
+    dp[1] /= p->rho0;
+    dp[2] /= p->rho0;
+}
+
+/* Contact response with the box walls: clamp each coordinate to [lo, hi]. */
+static void clamp_box(const orc_params *p, double *x)
+{
+    for (int d = 0; d < 3; ++d) {
+        if (x[d] < p->lo[d]) x[d] = p->lo[d];
+        if (x[d] > p->hi[d]) x[d] = p->hi[d];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* levels (Eq. 8, adaption model of Section 4.1)                       */
+/* ------------------------------------------------------------------ */
+
+int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+{
+    for (int32_t i = 0; i < p->n; ++i) {
+        int32_t L;
+        if (lod->mode == 0) {
+            L = p->n_max;
+        } else if (lod->mode == 1) {
+            L = lod->levels[i];
+        } else {
+            const double *xi = x + 3 * (int64_t)i;
+            double dx = xi[0] - lod->camera[0], dy = xi[1] - lod->camera[1],
+                   dz = xi[2] - lod->camera[2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            double t = (d - lod->d_near) / (lod->d_far - lod->d_near);
+            if (t < 0.0) t = 0.0;
+            if (t > 1.0) t = 1.0;
+            L = p->n_max - (int32_t)floor(t * (double)(p->n_max - p->n_min + 1));
+            if (L < p->n_min) L = p->n_min;
+            if (L > p->n_max) L = p->n_max;
+        }
+        if (L < 1 || L < p->n_min || L > p->n_max) return ORC_ERR_ARG;
+        lev[i] = L;
+    }
+    return ORC_OK;
+}
+
+static int check_params(const orc_params *p)
+{
+    if (p->n < 0 || p->n_min < 1 || p->n_max < p->n_min || !(p->h > 0) || !(p->rho0 > 0) ||
+        !(p->mass > 0) || !(p->eps >= 0) || !(p->dt > 0))
+        return ORC_ERR_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (p->dims[d] < 1 || !(p->hi[d] >= p->lo[d])) return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+/* Shared front half of a step: forces + prediction + clamp (Fig. 7, first
+ * loop), cell keys, counting sort and neighbour sets (second loop). */
+static int predict_and_neighbours(const orc_params *p, const double *x, double *v, double *xs,
+                                  uint32_t *keys, int32_t *perm, int64_t **off, int32_t **ids)
+{
+    const int32_t n = p->n;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int d = 0; d < 3; ++d) {
+            v[3 * (int64_t)i + d] += p->dt * p->g[d];
+            xs[3 * (int64_t)i + d] = x[3 * (int64_t)i + d] + p->dt * v[3 * (int64_t)i + d];
+        }
+        clamp_box(p, xs + 3 * (int64_t)i);
+    }
+    orc_cell_keys(p, xs, keys);
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_cells(p) + 1));
+    if (!start) return ORC_ERR_MEM;
+    int rc = orc_counting_sort(p, keys, perm, start);
+    if (rc == ORC_OK) rc = find_neighbours(p, xs, perm, start, off, ids);
+    free(start);
+    return rc;
+}
+
+static void copy_trace_neighbours(const orc_params *p, orc_trace *tr, const int64_t *off,
+                                  const int32_t *ids)
+{
+    if (!tr) return;
+    tr->nbr_total = off[p->n];
+    if (tr->nbr_count)
+        for (int32_t i = 0; i < p->n; ++i) tr->nbr_count[i] = (int32_t)(off[i + 1] - off[i]);
+    if (tr->nbr_ids && tr->nbr_cap >= off[p->n])
+        memcpy(tr->nbr_ids, ids, sizeof(int32_t) * (size_t)off[p->n]);
+}
+
+/* ------------------------------------------------------------------ */
+/* one APBF step (Fig. 7)                                              */
+/* ------------------------------------------------------------------ */
+
+/* x, v: n*3 doubles in particle-ID order, advanced in place by one step.
+ * tr may be NULL; any of its pointers may be NULL. */
+int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v, orc_trace *tr)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int32_t n = p->n;
+    const int32_t K = p->n_max;
+    size_t n3 = (size_t)n * 3;
+    int32_t *lev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    double *xs = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+    double *dp = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+    double *lam = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int64_t *off = NULL;
+    int32_t *ids = NULL;
+    if (!lev || !xs || !dp || !lam || !keys || !perm) { rc = ORC_ERR_MEM; goto done; }
+
+    /* levels from the positions at the start of the step */
+    rc = orc_levels(p, lod, x, lev);
+    if (rc) goto done;
+
+    rc = predict_and_neighbours(p, x, v, xs, keys, perm, &off, &ids);
+    if (rc) goto done;
+
+    if (tr) {
+        if (tr->levels) memcpy(tr->levels, lev, sizeof(int32_t) * (size_t)n);
+        if (tr->keys) memcpy(tr->keys, keys, sizeof(uint32_t) * (size_t)n);
+        if (tr->perm) memcpy(tr->perm, perm, sizeof(int32_t) * (size_t)n);
+        copy_trace_neighbours(p, tr, off, ids);
+        if (tr->xs_iter) memcpy(tr->xs_iter, xs, sizeof(double) * n3);
+    }
+
+    /* solver iterations: particle i is active in iteration k while k < N_i */
+    for (int32_t k = 0; k < K; ++k) {
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i)
+            if (lev[i] > k) lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i)
+            if (lev[i] > k) delta_p_of(p, xs, lam, i, ids + off[i], off[i + 1] - off[i], dp + 3 * (int64_t)i);
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i)
+            if (lev[i] > k) {
+                for (int d = 0; d < 3; ++d) xs[3 * (int64_t)i + d] += dp[3 * (int64_t)i + d];
+                clamp_box(p, xs + 3 * (int64_t)i);
+            }
+        if (tr && tr->lambda_iter) memcpy(tr->lambda_iter + (size_t)k * n, lam, sizeof(double) * (size_t)n);
+        if (tr && tr->xs_iter) memcpy(tr->xs_iter + (size_t)(k + 1) * n3, xs, sizeof(double) * n3);
+    }
+
+    /* velocity and position update for every particle */
+    for (size_t e = 0; e < n3; ++e) {
+        v[e] = (xs[e] - x[e]) / p->dt;
+        x[e] = xs[e];
+    }
+done:
+    free(lev); free(xs); free(dp); free(lam); free(keys); free(perm); free(off); free(ids);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* one plain PBF step, its own loop without gating                     */
+/* ------------------------------------------------------------------ */
+
+int orc_pbf_step(const orc_params *p, int32_t iters, double *x, double *v)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (iters < 0) return ORC_ERR_ARG;
+    const int32_t n = p->n;
+    size_t n3 = (size_t)n * 3;
+    double *xs = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+    double *dp = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+    double *lam = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int64_t *off = NULL;
+    int32_t *ids = NULL;
+    if (!xs || !dp || !lam || !keys || !perm) { rc = ORC_ERR_MEM; goto done; }
+    rc = predict_and_neighbours(p, x, v, xs, keys, perm, &off, &ids);
+    if (rc) goto done;
+    for (int32_t it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i)
+            lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i)
+            delta_p_of(p, xs, lam, i, ids + off[i], off[i + 1] - off[i], dp + 3 * (int64_t)i);
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) xs[3 * (int64_t)i + d] += dp[3 * (int64_t)i + d];
+            clamp_box(p, xs + 3 * (int64_t)i);
+        }
+    }
+    for (size_t e = 0; e < n3; ++e) {
+        v[e] = (xs[e] - x[e]) / p->dt;
+        x[e] = xs[e];
+    }
+done:
+    free(xs); free(dp); free(lam); free(keys); free(perm); free(off); free(ids);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* SPH density of every particle at given positions (Eq. 6), for the   */
+/* average-density report; neighbours by the same grid search.         */
+/* ------------------------------------------------------------------ */
+
+int orc_density(const orc_params *p, const double *x, double *rho)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int32_t n = p->n;
+    uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_cells(p) + 1));
+    int64_t *off = NULL;
+    int32_t *ids = NULL;
+    if (!keys || !perm || !start) { rc = ORC_ERR_MEM; goto done; }
+    orc_cell_keys(p, x, keys);
+    rc = orc_counting_sort(p, keys, perm, start);
+    if (rc) goto done;
+    rc = find_neighbours(p, x, perm, start, &off, &ids);
+    if (rc) goto done;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int32_t i = 0; i < n; ++i) {
+        double r = p->mass * orc_poly6(0.0, p->h);
+        const double *xi = x + 3 * (int64_t)i;
+        for (int64_t q = off[i]; q < off[i + 1]; ++q) {
+            const double *xj = x + 3 * (int64_t)ids[q];
+            double d0 = xi[0] - xj[0], d1 = xi[1] - xj[1], d2 = xi[2] - xj[2];
+            r += p->mass * orc_poly6(d0 * d0 + d1 * d1 + d2 * d2, p->h);
+        }
+        rho[i] = r;
+    }
+done:
+    free(keys); free(perm); free(start); free(off); free(ids);
+    return rc;
+}
+
+void orc_set_threads(int32_t t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+int32_t orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
