@@ -1,0 +1,229 @@
+"""Throughput of the adaptive PBF step on one MI355X.
+
+Workload: the 1,048,576-particle tank (128 x 64 x 128 lattice, spacing
+0.05, h = 0.1, velocities N(0, 0.1^2), box 6.4^3) with distance-to-camera
+levels N_i in {5..10}.  One step = the whole hot path: levels, forces and
+prediction, counting sort of cell keys with reorder, neighbour lists, level
+buckets, the gated lambda / correction iterations, velocity and position
+update.  Inputs are resident in HBM before the timed region; every step is
+one hipGraph replay on the context's stream.
+
+Prints ONE JSON line: particle-iterations/s (sum over steps of sum_i N_i,
+counted on the device, divided by the timed wall time), ms/step, the same
+for plain PBF with N = 10 and N = 5 on the same scene, the roofline of the
+dominant kernel from HIP events around each of its launches, and the FP64
+oracle's rate on the host cores over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "particle-iterations/s and ms/step at 1M particles, APBF vs PBF(N=10)"
+
+# FP32 operations per (active particle, neighbour) pair as written in the
+# kernels: lambda pass 27 (difference 3, |d|^2 5, poly6 term 4, rsqrt and
+# r 2, spiky factor 4, gradient sum 6, squared norm 3); update pass 22
+# (difference 3, |d|^2 5, rsqrt and r 2, spiky factor 4, lambda sum and
+# scale 2, correction sum 6).
+FLOP_PER_PAIR = {"lambda": 27.0, "update": 22.0}
+# compulsory HBM bytes per active particle: lambda reads x* (16) and
+# writes lambda (4); update reads x* and lambda (16 + 4) and writes x* (16)
+BYTES_PER_ACTIVE = {"lambda": 20.0, "update": 36.0}
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3  # published vector FP32 peak (counts dual-issue)
+
+
+def _timed_run(sim, steps, warmup, stream, torch):
+    sim.set_graph(True)
+    sim.step(warmup)
+    sim.sync()
+    pit0 = sim.stats()["total_particle_iterations"] if warmup else 0
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        evs[k].record(stream)
+        sim.step(1)
+    evs[steps].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    total_ms = float(evs[0].elapsed_time(evs[steps]))
+    sim.sync()
+    st = sim.stats()
+    pit = st["total_particle_iterations"] - pit0
+    return {"ms_per_step": total_ms / steps, "ms_median": float(np.median(per)),
+            "wall_s": wall, "particle_iterations": int(pit),
+            "value": pit / (total_ms * 1e-3), "mean_levels": pit / (steps * sim.n),
+            "max_neighbours": st["max_neighbours"]}
+
+
+def _profile(sc, steps, Sim, stream):
+    """Per-kernel HIP-event timings over `steps` direct-launch steps, plus
+    the exact pair counts of every lambda/update launch."""
+    sim = Sim(sc, stream=stream)
+    sim.step(2)  # same warm start as the timed run's graphs
+    sim.sync()
+    sim.profile_enable(True)
+    pairs = {"lambda": 0, "update": 0}
+    active = {"lambda": 0, "update": 0}
+    launches = 0
+    for _ in range(steps):
+        sim.step(1)
+        lv = sim.debug_levels().astype(np.int64)
+        cnt = sim.debug_neighbour_counts().astype(np.int64)
+        K = int(sc.n_max)
+        for k in range(K):
+            act = lv > k
+            pairs["lambda"] += int(cnt[act].sum())
+            pairs["update"] += int(cnt[act].sum())
+            active["lambda"] += int(act.sum())
+            active["update"] += int(act.sum())
+        launches += K
+    prof = sim.profile_read()
+    sim.close()
+    return prof, pairs, active, launches
+
+
+def _roofline(prof, pairs, active):
+    tot = {k: v[0] for k, v in prof.items()}
+    dom = max(("lambda", "update"), key=lambda k: tot[k])
+    ms, n_launch = prof[dom]
+    avg_s = ms * 1e-3 / n_launch
+    flops = FLOP_PER_PAIR[dom] * pairs[dom] / n_launch
+    bytes_ = BYTES_PER_ACTIVE[dom] * active[dom] / n_launch
+    tflops = flops / avg_s / 1e12
+    gbs = bytes_ / avg_s / 1e9
+    f_alu, f_hbm = tflops / PEAK_FP32_TFLOPS, gbs / PEAK_HBM_GBS
+    if f_alu >= f_hbm:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(f_alu, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(f_hbm, 4)}
+    roof.update({"kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+                 "algorithmic_bytes_per_launch": int(bytes_),
+                 "algorithmic_flop_per_launch": int(flops),
+                 "hbm_model_gbs": round(gbs, 1), "alu_tflops": round(tflops, 3),
+                 "traffic": None})
+    kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1],
+                   "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
+               for k, v in prof.items() if v[1]}
+    return roof, kernels
+
+
+def _cpu_baseline(sc, steps):
+    import oracle
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    oracle.set_threads(cores)
+    x, v = sc.x0.astype(np.float64), sc.v0.astype(np.float64)
+    pit = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lv = oracle.levels(sc, x)
+        pit += int(lv.sum())
+        x, v, _ = oracle.apbf_step(sc, x, v)
+    dt = time.perf_counter() - t0
+    return {"value": round(pit / dt, 1), "unit": "particle-iterations/s",
+            "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"first {steps} steps of the same 1,048,576-particle APBF workload "
+                      f"from the same initial state ({dt:.1f} s)",
+            "ms_per_step": round(1e3 * dt / steps, 1)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pbf", action="store_true", help="skip the PBF(10)/PBF(5) runs")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver has no multi-GPU path; see the design notes for how it would shard)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import scenes
+    from paper_1608_04721_amd import Sim, PBF_LOD_UNIFORM
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()  # default priority
+    sc = scenes.tank_1m()
+    steps, warm = args.steps, args.warmup
+
+    print(f"[bench] APBF {sc.name}: n={sc.n}, levels {sc.n_min}..{sc.n_max}", file=sys.stderr,
+          flush=True)
+    with Sim(sc, stream=stream) as sim:
+        apbf = _timed_run(sim, steps, warm, stream, torch)
+    out_pbf = {}
+    if not args.no_pbf:
+        for N in (10, 5):
+            scp = sc.with_lod(PBF_LOD_UNIFORM, n_min=N, n_max=N)
+            print(f"[bench] PBF N={N}", file=sys.stderr, flush=True)
+            with Sim(scp, stream=stream) as sim:
+                out_pbf[N] = _timed_run(sim, steps, warm, stream, torch)
+    print("[bench] profiling kernels", file=sys.stderr, flush=True)
+    prof, pairs, active, _ = _profile(sc, args.profile_steps, Sim, stream)
+    roof, kernels = _roofline(prof, pairs, active)
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        cpu = _cpu_baseline(sc, args.cpu_steps)
+
+    line = {
+        "metric": METRIC,
+        "value": round(apbf["value"], 1),
+        "unit": "particle-iterations/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(apbf["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "tank_1m: 1,048,576 particles (128x64x128 lattice, s=0.05, "
+                               "h=0.1, v~N(0,0.1^2)), box 6.4^3, distance-to-camera levels "
+                               "5..10, dt=1/60",
+                   "particles": sc.n, "levels": [sc.n_min, sc.n_max], "lod": "dtc",
+                   "launch": "hipGraph per step"},
+        "ms_median": round(apbf["ms_median"], 4),
+        "mean_levels": round(apbf["mean_levels"], 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    if out_pbf:
+        line["pbf"] = {str(N): {"ms_per_step": round(r["ms_per_step"], 4),
+                                "ms_median": round(r["ms_median"], 4),
+                                "value": round(r["value"], 1)} for N, r in out_pbf.items()}
+        line["speedup_vs_pbf10"] = round(out_pbf[10]["ms_per_step"] / apbf["ms_per_step"], 4)
+        line["speedup_vs_pbf5"] = round(out_pbf[5]["ms_per_step"] / apbf["ms_per_step"], 4)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,211 @@
+/*
+ * libpbf — adaptive position-based fluids (APBF) time steps on one AMD
+ * Instinct MI355X (gfx950), behind a plain C ABI.
+ *
+ * Method: Koester & Krueger, "Adaptive Position-Based Fluids" (IJCGA 6(3),
+ * 2016).  One step follows the simulation loop of Section 5 (Fig. 7):
+ *   1. apply external forces and predict positions for every particle,
+ *   2. find neighbours of every particle (uniform grid built by a counting
+ *      sort of cell keys, particles reordered by cell, Section 6),
+ *   3. for iterations l = 1..N_l, for the active set P_l (Eqs. 9-10):
+ *      lambda_i (Eqs. 4-6), Delta p_i with contact response (Eq. 7),
+ *      position update; finished particles (Eq. 11) keep their position,
+ *   4. update velocity and position of every particle.
+ * Each particle's level N_i (Eq. 8), which is also its iteration count,
+ * comes from an explicit array, a uniform value, or the distance to a
+ * camera (DTC adaption model, Section 4.1).
+ *
+ * Readings taken where the paper leaves details open (identical in the FP64
+ * oracle that the test suite checks this library against):
+ *   - density kernel: poly6 W = 315/(64 pi h^9) (h^2 - r^2)^3, self term
+ *     included; gradient: spiky, -45/(pi h^6) (h - r)^2 d/r;
+ *   - uniform mass m: lambda_i = -C_i / ((m/rho0^2)(|sum_j gW|^2 +
+ *     sum_j |gW|^2) + eps), C_i = rho_i/rho0 - 1;
+ *     Delta p_i = (1/rho0) sum_j (lambda_i + lambda_j) gW_ij;
+ *   - neighbour sets N_i = { j != i : |x*_i - x*_j|^2 < h^2 } are found once
+ *     per step from the predicted positions and kept for every iteration;
+ *   - a finished particle keeps its last lambda, and active neighbours use it;
+ *   - contacts are the box walls: positions are clamped to [lo, hi] after
+ *     prediction and after every update;
+ *   - iteration k = 0..n_max-1 corrects particle i only while k < N_i.
+ *
+ * Conventions (every entry point):
+ *   - returns a pbf_status; nothing aborts or exits;
+ *   - argument checks run on the host before any HIP call; a failed check
+ *     leaves the context unchanged;
+ *   - positions/velocities cross the boundary as float[3*n], x/y/z
+ *     interleaved, in particle-ID order (batch: scenes concatenated in
+ *     scene order, particle IDs local to each scene);
+ *   - "on_device" flags say whether a caller pointer is device memory
+ *     (hipMalloc / torch) or host memory; caller buffers are borrowed only
+ *     for the duration of the call; the library owns all its device state;
+ *   - one context = one HIP stream; work is enqueued asynchronously on it;
+ *     calls that return data to host memory synchronise that stream;
+ *   - faults detected on the device (neighbour capacity, non-finite
+ *     positions) are latched and reported by the next synchronising call;
+ *   - a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef PBF_H
+#define PBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbf_ctx pbf_ctx; /* opaque; owns every device buffer it uses */
+
+typedef enum {
+    PBF_OK = 0,
+    PBF_ERR_INVALID_ARG = -1,   /* bad argument or parameter; nothing changed */
+    PBF_ERR_NONFINITE = -2,     /* NaN/Inf in inputs, or positions became non-finite */
+    PBF_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed */
+    PBF_ERR_DEVICE = -4,        /* a HIP call failed (message in pbf_last_error) */
+    PBF_ERR_CAPACITY = -5       /* a particle exceeded the neighbour capacity, or a
+                                   grid cell held more than PBF_MAX_CELL particles */
+} pbf_status;
+
+#define PBF_MAX_ITERS 32          /* largest iteration count / level */
+#define PBF_MAX_CELL 4096         /* largest particle count of one grid cell */
+#define PBF_DEFAULT_NEIGHBOURS 96 /* per-particle neighbour capacity if 0 is given */
+#define PBF_MAX_SCENES 65535
+
+/* LOD (level) modes, Section 4.1 / Eq. 8 */
+#define PBF_LOD_UNIFORM 0  /* N_i = n_max for every particle: plain PBF */
+#define PBF_LOD_EXPLICIT 1 /* N_i from a caller array (particle-ID order) */
+#define PBF_LOD_DTC 2      /* distance to camera, recomputed each step from the
+                              positions at the start of the step */
+
+/* Per-scene parameters.  All lengths in the same unit as positions. */
+typedef struct pbf_params {
+    int32_t n;              /* particles, >= 0 */
+    int32_t n_min, n_max;   /* level range, 1 <= n_min <= n_max <= PBF_MAX_ITERS */
+    int32_t grid_dims[3];   /* cells per axis (edge h from box_lo); 0 => ceil(extent/h) */
+    float box_lo[3], box_hi[3]; /* walls; box_hi >= box_lo per axis */
+    float h;                /* smoothing length = cell edge, > 0 */
+    float rho0;             /* rest density, > 0 */
+    float mass;             /* particle mass, > 0 */
+    float eps;              /* relaxation added to lambda's denominator, >= 0 */
+    float dt;               /* time step, > 0 */
+    float gravity[3];       /* external acceleration */
+    int32_t max_neighbours; /* neighbour capacity; 0 => PBF_DEFAULT_NEIGHBOURS; the
+                               context uses the largest value over its scenes */
+    uint32_t flags;         /* reserved, must be 0 */
+} pbf_params;
+
+/* Level source (Section 4.1).  DTC: t = clamp((|x - camera| - d_near) /
+ * (d_far - d_near), 0, 1), N = clamp(n_max - floor(t (n_max - n_min + 1)),
+ * n_min, n_max): near particles iterate n_max times, far ones n_min. */
+typedef struct pbf_lod_desc {
+    int32_t mode;            /* PBF_LOD_* */
+    const uint8_t *levels;   /* EXPLICIT: n levels in [n_min, n_max], particle-ID order */
+    int32_t levels_on_device;
+    float camera[3];         /* DTC */
+    float d_near, d_far;     /* DTC: d_far > d_near */
+} pbf_lod_desc;
+
+/* Statistics of the most recent step (read with pbf_stats; synchronises). */
+typedef struct pbf_step_stats {
+    int32_t n_iters;                     /* loop bound: largest n_max over scenes */
+    int64_t active[PBF_MAX_ITERS];       /* |P_k| for k = 0..n_iters-1 */
+    int64_t particle_iterations;         /* sum_i N_i = sum_k |P_k| */
+    int64_t neighbour_pairs;             /* sum_i |N_i| */
+    int32_t max_neighbours;              /* largest |N_i| */
+    int64_t total_particle_iterations;   /* sum over every step since create or
+                                            pbf_set_state, counted on the device */
+    int64_t total_steps;                 /* steps counted in the same span */
+} pbf_step_stats;
+
+/* ---------------- core entry points ---------------- */
+
+/* One scene.  x0, v0: float[3n] in ID order, copied.  hip_stream: a
+ * hipStream_t (NULL => the library creates its own non-blocking stream).
+ * The new context starts with PBF_LOD_UNIFORM. */
+pbf_status pbf_create(const pbf_params *params, const float *x0, const float *v0,
+                      int32_t inputs_on_device, void *hip_stream, pbf_ctx **out);
+
+/* Set the level source (scene 0 of a context); applies from the next step.
+ * EXPLICIT levels are copied. */
+pbf_status pbf_set_lod(pbf_ctx *ctx, const pbf_lod_desc *lod);
+
+/* Advance every scene of the context by n_steps >= 0 steps; asynchronous. */
+pbf_status pbf_step(pbf_ctx *ctx, int32_t n_steps);
+
+/* Positions float[3 * n_total] in ID order (scenes concatenated) into a
+ * caller buffer.  Host buffers synchronise the stream first. */
+pbf_status pbf_read_positions(pbf_ctx *ctx, float *out, int32_t out_on_device);
+
+/* Velocities, same layout and rules as pbf_read_positions. */
+pbf_status pbf_read_velocities(pbf_ctx *ctx, float *out, int32_t out_on_device);
+
+/* Wait for the stream; report latched device faults (CAPACITY, NONFINITE). */
+pbf_status pbf_sync(pbf_ctx *ctx);
+
+void pbf_destroy(pbf_ctx *ctx);
+const char *pbf_last_error(const pbf_ctx *ctx);  /* never NULL */
+const char *pbf_status_string(pbf_status s);     /* never NULL */
+
+/* ---------------- batched scenes ---------------- */
+
+/* n_scenes independent scenes in one context, advanced together: every
+ * kernel of a step covers all scenes at once (one launch per pass).
+ * params: n_scenes entries; x0, v0: float[3 * sum n] with scenes
+ * concatenated in order. */
+pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const float *x0,
+                            const float *v0, int32_t inputs_on_device, void *hip_stream,
+                            pbf_ctx **out);
+pbf_status pbf_batch_set_lod(pbf_ctx *ctx, int32_t scene, const pbf_lod_desc *lod);
+/* Positions of one scene, float[3 * n_scene] in its ID order. */
+pbf_status pbf_batch_read_positions(pbf_ctx *ctx, int32_t scene, float *out,
+                                    int32_t out_on_device);
+pbf_status pbf_get_counts(const pbf_ctx *ctx, int32_t *n_scenes, int64_t *n_total);
+
+/* ---------------- execution control ---------------- */
+
+/* enable != 0: each step is captured once into a hipGraph (one per buffer
+ * parity) and replayed; 0: kernels are launched one by one. */
+pbf_status pbf_set_graph(pbf_ctx *ctx, int32_t enable);
+
+/* Launch shape of one kernel class (threads per block, a multiple of 64 in
+ * [64, 1024]); 0 restores the default.  Kernel classes are numbered
+ * 0..pbf_kernel_count()-1 and named by pbf_kernel_name(). */
+int32_t pbf_kernel_count(void);
+const char *pbf_kernel_name(int32_t kernel);  /* NULL if out of range */
+pbf_status pbf_set_block_size(pbf_ctx *ctx, int32_t kernel, int32_t threads);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * every launch (direct launches only; graph mode is switched off while
+ * enabled).  pbf_profile_read synchronises and returns, per kernel class,
+ * total milliseconds and launch counts accumulated since enabling. */
+pbf_status pbf_profile_enable(pbf_ctx *ctx, int32_t enable);
+pbf_status pbf_profile_read(pbf_ctx *ctx, double *total_ms, int64_t *launches, int32_t count);
+
+/* ---------------- state, statistics, debug (ID order, synchronising) --- */
+
+pbf_status pbf_stats(pbf_ctx *ctx, pbf_step_stats *out);
+/* Cell key of each particle's predicted position in the last step (key local
+ * to its scene's grid: (cz * dims_y + cy) * dims_x + cx). */
+pbf_status pbf_debug_keys(pbf_ctx *ctx, uint32_t *keys);
+/* Storage order after the last step's counting sort, as particle IDs
+ * (batch: global IDs = scene offset + local ID). */
+pbf_status pbf_debug_permutation(pbf_ctx *ctx, int32_t *ids);
+/* Neighbour sets of the last step: counts[n_total] and, if ids != NULL and
+ * cap >= total, ids of each particle's neighbours (global IDs, ascending),
+ * particle after particle.  *total receives the number of entries. */
+pbf_status pbf_debug_neighbours(pbf_ctx *ctx, int32_t *counts, int32_t *ids, int64_t cap,
+                                int64_t *total);
+/* Last lambda of every particle (from its last active iteration). */
+pbf_status pbf_debug_lambda(pbf_ctx *ctx, float *lambda);
+/* Levels N_i used in the last step. */
+pbf_status pbf_debug_levels(pbf_ctx *ctx, uint8_t *levels);
+/* Save / restore the dynamic state (positions and velocities, ID order,
+ * host buffers float[3 * n_total] each, plus the step counter).  A restored
+ * context continues bit-identically to one that never stopped. */
+pbf_status pbf_get_state(pbf_ctx *ctx, float *x, float *v, int64_t *step);
+pbf_status pbf_set_state(pbf_ctx *ctx, const float *x, const float *v, int64_t step);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBF_H */

@@ -1,0 +1,788 @@
+// Host side of libpbf: contexts, argument checks, device buffers, graph
+// capture, profiling and the ID-order debug exports declared in pbf.h.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pbf.h"
+#include "pbf_internal.h"
+
+namespace pbf {
+
+struct Timer {
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pool;
+    size_t used = 0;
+    double total_ms[K_COUNT] = {};
+    int64_t launches[K_COUNT] = {};
+    hipError_t status = hipSuccess;
+};
+
+void timer_begin(Timer *tm, int kernel, hipStream_t s)
+{
+    if (tm->used == tm->pool.size()) {
+        Timer::Rec r{kernel, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+            tm->status = hipErrorOutOfMemory;
+            return;
+        }
+        tm->pool.push_back(r);
+    }
+    Timer::Rec &r = tm->pool[tm->used];
+    r.kernel = kernel;
+    hipError_t e = hipEventRecord(r.a, s);
+    if (e != hipSuccess) tm->status = e;
+}
+
+void timer_end(Timer *tm, int kernel, hipStream_t s)
+{
+    if (tm->used >= tm->pool.size()) return;
+    Timer::Rec &r = tm->pool[tm->used];
+    (void)kernel;
+    hipError_t e = hipEventRecord(r.b, s);
+    if (e != hipSuccess) tm->status = e;
+    tm->used++;
+}
+
+static hipError_t timer_collect(Timer *tm, hipStream_t s)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < tm->used; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, tm->pool[i].a, tm->pool[i].b);
+        if (e != hipSuccess) return e;
+        tm->total_ms[tm->pool[i].kernel] += ms;
+        tm->launches[tm->pool[i].kernel] += 1;
+    }
+    tm->used = 0;
+    return hipSuccess;
+}
+
+}  // namespace pbf
+
+using namespace pbf;
+
+struct pbf_ctx {
+    int32_t n_scenes = 0;
+    int64_t n_total = 0;
+    std::vector<pbf_params> params;
+    std::vector<int64_t> pid_off;  // n_scenes + 1
+    std::vector<SceneDev> scenes;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    StepBuffers b{};
+    int cur = 0;
+    int64_t step = 0;
+    bool stepped = false;
+    LaunchShape ls{};
+    bool graph = false;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool profiling = false;
+    Timer timer;
+    float *staging = nullptr;  // float[3 n_total], device
+    std::vector<void *> allocs;
+    std::string err;
+};
+
+namespace {
+
+pbf_status fail(pbf_ctx *c, pbf_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+pbf_status hip_fail(pbf_ctx *c, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(c, PBF_ERR_OUT_OF_MEMORY, m);
+    return fail(c, PBF_ERR_DEVICE, m);
+}
+
+#define HIPCHK(C, EXPR, WHAT)                         \
+    do {                                              \
+        hipError_t e_ = (EXPR);                       \
+        if (e_ != hipSuccess) return hip_fail(C, e_, WHAT); \
+    } while (0)
+
+bool finite3(const float *p)
+{
+    return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]);
+}
+
+// ceil(extent / h) with a relative slack of 1e-9, at least 1
+int32_t auto_dim(float lo, float hi, float h)
+{
+    double q = ((double)hi - (double)lo) / (double)h;
+    double d = std::ceil(q * (1.0 - 1e-9));
+    return d < 1.0 ? 1 : (int32_t)d;
+}
+
+pbf_status check_params(const pbf_params &p, int32_t idx, std::string &msg, int32_t dims[3])
+{
+    char buf[256];
+    auto bad = [&](const char *what) {
+        std::snprintf(buf, sizeof buf, "scene %d: %s", idx, what);
+        msg = buf;
+        return PBF_ERR_INVALID_ARG;
+    };
+    if (p.n < 0) return bad("n < 0");
+    if (p.n_min < 1 || p.n_max < p.n_min || p.n_max > PBF_MAX_ITERS)
+        return bad("need 1 <= n_min <= n_max <= PBF_MAX_ITERS");
+    const float fs[] = {p.h, p.rho0, p.mass, p.eps, p.dt, p.gravity[0], p.gravity[1],
+                        p.gravity[2], p.box_lo[0], p.box_lo[1], p.box_lo[2], p.box_hi[0],
+                        p.box_hi[1], p.box_hi[2]};
+    for (float f : fs)
+        if (!std::isfinite(f)) return bad("non-finite parameter");
+    if (!(p.h > 0.f) || !(p.rho0 > 0.f) || !(p.mass > 0.f) || !(p.eps >= 0.f) || !(p.dt > 0.f))
+        return bad("need h, rho0, mass, dt > 0 and eps >= 0");
+    if (p.flags != 0) return bad("flags must be 0");
+    if (p.max_neighbours < 0 || p.max_neighbours > 4096) return bad("max_neighbours outside [0, 4096]");
+    for (int d = 0; d < 3; ++d) {
+        if (!(p.box_hi[d] >= p.box_lo[d])) return bad("box_hi < box_lo");
+        if (p.grid_dims[d] < 0) return bad("grid_dims < 0");
+        dims[d] = p.grid_dims[d] ? p.grid_dims[d] : auto_dim(p.box_lo[d], p.box_hi[d], p.h);
+        if (dims[d] > (1 << 20)) return bad("grid too large");
+    }
+    return PBF_OK;
+}
+
+SceneDev make_scene(const pbf_params &p, const int32_t dims[3], uint32_t cell_off,
+                    uint32_t pid_off)
+{
+    SceneDev s{};
+    const double h = p.h, pi = 3.14159265358979323846;
+    for (int d = 0; d < 3; ++d) {
+        s.lo[d] = p.box_lo[d];
+        s.hi[d] = p.box_hi[d];
+        s.g[d] = p.gravity[d];
+        s.dims[d] = dims[d];
+        s.cam[d] = 0.f;
+    }
+    s.h = p.h;
+    s.h2 = (float)(h * h);
+    s.h6 = (float)std::pow(h, 6);
+    s.c_rho = (float)((double)p.mass * 315.0 / (64.0 * pi * std::pow(h, 9)) / (double)p.rho0);
+    s.c_grad = (float)(45.0 / (pi * std::pow(h, 6)));
+    s.c_s = (float)((double)p.mass / ((double)p.rho0 * (double)p.rho0));
+    s.inv_rho0 = (float)(1.0 / (double)p.rho0);
+    s.eps = p.eps;
+    s.dt = p.dt;
+    s.inv_dt = (float)(1.0 / (double)p.dt);
+    s.cell_off = cell_off;
+    s.pid_off = pid_off;
+    s.n_min = p.n_min;
+    s.n_max = p.n_max;
+    s.lod_mode = PBF_LOD_UNIFORM;
+    s.d_near = 0.f;
+    s.d_far = 1.f;
+    return s;
+}
+
+template <class T>
+hipError_t dalloc(pbf_ctx *c, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+        c->allocs.push_back(q);
+        *p = (T *)q;
+    }
+    return e;
+}
+
+void drop_graphs(pbf_ctx *c)
+{
+    for (auto &g : c->exec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+bool fixed_shape(int k)
+{
+    return k == K_SCAN_REDUCE || k == K_SCAN_TOP || k == K_SCAN_APPLY || k == K_LEVEL_COUNT ||
+           k == K_LEVEL_SCAN || k == K_LEVEL_SCATTER;
+}
+
+pbf_status latched(pbf_ctx *c)
+{
+    uint32_t e = 0;
+    HIPCHK(c, hipMemcpyAsync(&e, c->b.err, sizeof e, hipMemcpyDeviceToHost, c->stream),
+           "read fault word");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (e & ERR_NONFINITE) return fail(c, PBF_ERR_NONFINITE, "positions became non-finite");
+    if (e & ERR_NEIGHBOUR_CAP)
+        return fail(c, PBF_ERR_CAPACITY, "a particle exceeded the neighbour capacity");
+    if (e & ERR_CELL_CAP)
+        return fail(c, PBF_ERR_CAPACITY, "a grid cell held more than PBF_MAX_CELL particles");
+    return PBF_OK;
+}
+
+// Upload x, v (float[3 n_total], ID order, host) as the current state with
+// storage order = ID order.
+pbf_status upload_state(pbf_ctx *c, const float *x, const float *v)
+{
+    const int64_t n = c->n_total;
+    std::vector<float4> hx((size_t)n), hv((size_t)n);
+    std::vector<uint32_t> hid((size_t)n);
+    for (int32_t s = 0; s < c->n_scenes; ++s) {
+        float sbits;
+        int32_t si = s;
+        std::memcpy(&sbits, &si, sizeof sbits);
+        for (int64_t g = c->pid_off[s]; g < c->pid_off[s + 1]; ++g) {
+            hx[g] = make_float4(x[3 * g], x[3 * g + 1], x[3 * g + 2], sbits);
+            hv[g] = make_float4(v[3 * g], v[3 * g + 1], v[3 * g + 2], 0.f);
+            hid[g] = (uint32_t)g;
+        }
+    }
+    c->cur = 0;
+    HIPCHK(c, hipMemcpyAsync(c->b.x[0], hx.data(), n * sizeof(float4), hipMemcpyHostToDevice, c->stream), "upload x");
+    HIPCHK(c, hipMemcpyAsync(c->b.v[0], hv.data(), n * sizeof(float4), hipMemcpyHostToDevice, c->stream), "upload v");
+    HIPCHK(c, hipMemcpyAsync(c->b.id[0], hid.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream), "upload id");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return PBF_OK;
+}
+
+// Copy a caller buffer (host or device) of `bytes` into host memory.
+pbf_status fetch_input(pbf_ctx *c, const void *src, size_t bytes, int on_device, void *dst)
+{
+    if (bytes == 0) return PBF_OK;
+    if (!on_device) {
+        std::memcpy(dst, src, bytes);
+        return PBF_OK;
+    }
+    HIPCHK(c, hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "copy device input");
+    return PBF_OK;
+}
+
+pbf_status check_levels(pbf_ctx *c, int32_t scene, const uint8_t *lv)
+{
+    const pbf_params &p = c->params[scene];
+    for (int32_t i = 0; i < p.n; ++i)
+        if (lv[i] < p.n_min || lv[i] > p.n_max)
+            return fail(c, PBF_ERR_INVALID_ARG, "explicit level outside [n_min, n_max]");
+    return PBF_OK;
+}
+
+pbf_status read_by_id(pbf_ctx *c, const float4 *src, float *out, int on_device, int64_t id_lo,
+                      int64_t id_hi)
+{
+    float *dst = on_device ? out : c->staging;
+    HIPCHK(c, enqueue_unpermute(c->n_total, src, c->b.id[c->cur], dst, (uint32_t)id_lo,
+                                (uint32_t)id_hi, c->stream), "unpermute");
+    if (!on_device) {
+        HIPCHK(c, hipMemcpyAsync(out, c->staging, (size_t)(id_hi - id_lo) * 3 * sizeof(float),
+                                 hipMemcpyDeviceToHost, c->stream), "copy out");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+        return latched(c);
+    }
+    return PBF_OK;
+}
+
+template <class T>
+pbf_status d2h(pbf_ctx *c, std::vector<T> &dst, const T *src, size_t count)
+{
+    dst.resize(count);
+    if (count == 0) return PBF_OK;
+    HIPCHK(c, hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, c->stream),
+           "copy to host");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return PBF_OK;
+}
+
+pbf_status need_step(pbf_ctx *c)
+{
+    if (!c->stepped) return fail(c, PBF_ERR_INVALID_ARG, "no step has run since the state was set");
+    return PBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pbf_status_string(pbf_status s)
+{
+    switch (s) {
+    case PBF_OK: return "ok";
+    case PBF_ERR_INVALID_ARG: return "invalid argument";
+    case PBF_ERR_NONFINITE: return "non-finite value";
+    case PBF_ERR_OUT_OF_MEMORY: return "out of memory";
+    case PBF_ERR_DEVICE: return "device error";
+    case PBF_ERR_CAPACITY: return "capacity exceeded";
+    }
+    return "unknown status";
+}
+
+const char *pbf_last_error(const pbf_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+int32_t pbf_kernel_count(void) { return K_COUNT; }
+
+const char *pbf_kernel_name(int32_t k)
+{
+    return (k >= 0 && k < K_COUNT) ? kKernelNames[k] : nullptr;
+}
+
+void pbf_destroy(pbf_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (auto &r : c->timer.pool) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const float *x0,
+                            const float *v0, int32_t inputs_on_device, void *hip_stream,
+                            pbf_ctx **out)
+{
+    if (!out) return PBF_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_scenes < 1 || n_scenes > PBF_MAX_SCENES || !params) return PBF_ERR_INVALID_ARG;
+    // ---- host-side checks, before any HIP call
+    std::vector<std::array<int32_t, 3>> dims((size_t)n_scenes);
+    int64_t n_total = 0, cells = 0;
+    int32_t cap = 0, kmax = 1;
+    std::string msg;
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        if (check_params(params[s], s, msg, dims[s].data()) != PBF_OK) return PBF_ERR_INVALID_ARG;
+        n_total += params[s].n;
+        cells += (int64_t)dims[s][0] * dims[s][1] * dims[s][2];
+        cap = std::max(cap, params[s].max_neighbours ? params[s].max_neighbours
+                                                     : PBF_DEFAULT_NEIGHBOURS);
+        kmax = std::max(kmax, params[s].n_max);
+    }
+    if (n_total >= ((int64_t)1 << 31) || cells >= ((int64_t)1 << 32) - 2)
+        return PBF_ERR_INVALID_ARG;
+    if (n_total > 0 && (!x0 || !v0)) return PBF_ERR_INVALID_ARG;
+
+    pbf_ctx *c = new (std::nothrow) pbf_ctx();
+    if (!c) return PBF_ERR_OUT_OF_MEMORY;
+    c->n_scenes = n_scenes;
+    c->n_total = n_total;
+    c->params.assign(params, params + n_scenes);
+    c->pid_off.assign((size_t)n_scenes + 1, 0);
+    for (int32_t s = 0; s < n_scenes; ++s) c->pid_off[s + 1] = c->pid_off[s] + params[s].n;
+    for (int k = 0; k < K_COUNT; ++k) c->ls.block[k] = kDefaultBlock[k];
+
+    std::vector<float> hx((size_t)n_total * 3), hv((size_t)n_total * 3);
+    pbf_status st = fetch_input(c, x0, hx.size() * sizeof(float), inputs_on_device, hx.data());
+    if (st == PBF_OK) st = fetch_input(c, v0, hv.size() * sizeof(float), inputs_on_device, hv.data());
+    if (st != PBF_OK) {
+        pbf_status r = st;
+        pbf_destroy(c);
+        return r;
+    }
+    for (int64_t i = 0; i < n_total; ++i)
+        if (!finite3(&hx[3 * i]) || !finite3(&hv[3 * i])) {
+            pbf_destroy(c);
+            return PBF_ERR_NONFINITE;
+        }
+
+    auto bail = [&](pbf_status s) {
+        pbf_destroy(c);
+        return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(PBF_ERR_DEVICE);
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(PBF_ERR_DEVICE);
+        c->own_stream = true;
+    }
+
+    uint32_t coff = 0;
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        c->scenes.push_back(make_scene(params[s], dims[s].data(), coff, (uint32_t)c->pid_off[s]));
+        coff += (uint32_t)((int64_t)dims[s][0] * dims[s][1] * dims[s][2]);
+    }
+
+    StepBuffers &b = c->b;
+    const size_t n = (size_t)n_total;
+    b.n = n_total;
+    b.n_cells = (uint32_t)cells;
+    b.n_iters = kmax;
+    b.nbr_cap = cap;
+    b.n_level_blocks = (int32_t)((n_total + kLevelBlock - 1) / kLevelBlock);
+    b.n_scan_blocks = (int32_t)((cells + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems));
+    SceneDev *dsc = nullptr;
+    uint8_t *dlev = nullptr;
+    hipError_t e = hipSuccess;
+#define AL(P, N) if (e == hipSuccess) e = dalloc(c, &(P), (N))
+    AL(dsc, (size_t)n_scenes);
+    AL(dlev, n);
+    for (int h = 0; h < 2; ++h) {
+        AL(b.x[h], n);
+        AL(b.v[h], n);
+        AL(b.id[h], n);
+        AL(b.lvl[h], n);
+        AL(b.xs[h], n);
+    }
+    AL(b.xs_pred, n);
+    AL(b.key_pre, n);
+    AL(b.ticket, n);
+    AL(b.key, n);
+    AL(b.tmp_src, n);
+    AL(b.tmp_id, n);
+    AL(b.cell_count, (size_t)cells);
+    AL(b.cell_start, (size_t)cells + 1);
+    AL(b.scan_part, (size_t)b.n_scan_blocks);
+    AL(b.level_counts, (size_t)b.n_level_blocks * kmax);
+    AL(b.count_ge, (size_t)PBF_MAX_ITERS + 2);
+    AL(b.order, n);
+    AL(b.nbr, n * (size_t)cap);
+    AL(b.nmeta, n);
+    AL(b.err, 1);
+    AL(b.totals, 2);
+    AL(c->staging, n * 3);
+#undef AL
+    if (e != hipSuccess) return bail(hip_fail(c, e, "allocate") );
+    b.scenes = dsc;
+    b.lev_by_id = dlev;
+    if (hipMemcpy(dsc, c->scenes.data(), sizeof(SceneDev) * n_scenes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b.err, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(b.totals, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(dlev, 0, n ? n : 1) != hipSuccess)
+        return bail(PBF_ERR_DEVICE);
+    if (upload_state(c, hx.data(), hv.data()) != PBF_OK) return bail(PBF_ERR_DEVICE);
+    *out = c;
+    return PBF_OK;
+}
+
+pbf_status pbf_create(const pbf_params *params, const float *x0, const float *v0,
+                      int32_t inputs_on_device, void *hip_stream, pbf_ctx **out)
+{
+    return pbf_batch_create(1, params, x0, v0, inputs_on_device, hip_stream, out);
+}
+
+pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (!lod || scene < 0 || scene >= c->n_scenes)
+        return fail(c, PBF_ERR_INVALID_ARG, "bad scene index or null descriptor");
+    SceneDev s = c->scenes[scene];
+    const pbf_params &p = c->params[scene];
+    std::vector<uint8_t> lv;
+    if (lod->mode == PBF_LOD_EXPLICIT) {
+        if (p.n > 0 && !lod->levels) return fail(c, PBF_ERR_INVALID_ARG, "levels is NULL");
+        lv.resize((size_t)p.n);
+        pbf_status st = fetch_input(c, lod->levels, lv.size(), lod->levels_on_device, lv.data());
+        if (st != PBF_OK) return st;
+        st = check_levels(c, scene, lv.data());
+        if (st != PBF_OK) return st;
+    } else if (lod->mode == PBF_LOD_DTC) {
+        if (!finite3(lod->camera) || !std::isfinite(lod->d_near) || !std::isfinite(lod->d_far) ||
+            !(lod->d_far > lod->d_near))
+            return fail(c, PBF_ERR_INVALID_ARG, "DTC needs a finite camera and d_far > d_near");
+        for (int d = 0; d < 3; ++d) s.cam[d] = lod->camera[d];
+        s.d_near = lod->d_near;
+        s.d_far = lod->d_far;
+    } else if (lod->mode != PBF_LOD_UNIFORM) {
+        return fail(c, PBF_ERR_INVALID_ARG, "unknown LOD mode");
+    }
+    s.lod_mode = lod->mode;
+    c->scenes[scene] = s;
+    if (!lv.empty())
+        HIPCHK(c, hipMemcpyAsync(c->b.lev_by_id + c->pid_off[scene], lv.data(), lv.size(),
+                                 hipMemcpyHostToDevice, c->stream), "upload levels");
+    HIPCHK(c, hipMemcpyAsync((void *)(c->b.scenes + scene), &c->scenes[scene], sizeof(SceneDev),
+                             hipMemcpyHostToDevice, c->stream), "upload scene");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return PBF_OK;
+}
+
+pbf_status pbf_set_lod(pbf_ctx *c, const pbf_lod_desc *lod)
+{
+    return pbf_batch_set_lod(c, 0, lod);
+}
+
+pbf_status pbf_step(pbf_ctx *c, int32_t n_steps)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (n_steps < 0) return fail(c, PBF_ERR_INVALID_ARG, "n_steps < 0");
+    for (int32_t k = 0; k < n_steps; ++k) {
+        if (c->graph && !c->profiling && c->n_total > 0) {
+            hipGraphExec_t &g = c->exec[c->cur];
+            if (!g) {
+                hipGraph_t graph = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal),
+                       "begin capture");
+                hipError_t e = enqueue_step(c->b, c->cur, c->ls, c->stream, nullptr);
+                hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+                if (e != hipSuccess) return hip_fail(c, e, "capture step");
+                if (e2 != hipSuccess) return hip_fail(c, e2, "end capture");
+                e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    g = nullptr;
+                    return hip_fail(c, e, "instantiate graph");
+                }
+            }
+            HIPCHK(c, hipGraphLaunch(g, c->stream), "launch graph");
+        } else {
+            HIPCHK(c, enqueue_step(c->b, c->cur, c->ls, c->stream,
+                                   c->profiling ? &c->timer : nullptr), "enqueue step");
+            if (c->profiling) {
+                if (c->timer.status != hipSuccess) return hip_fail(c, c->timer.status, "profiling events");
+                HIPCHK(c, timer_collect(&c->timer, c->stream), "collect timings");
+            }
+        }
+        c->cur ^= 1;
+        c->step += 1;
+        c->stepped = true;
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_sync(pbf_ctx *c)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return latched(c);
+}
+
+pbf_status pbf_read_positions(pbf_ctx *c, float *out, int32_t on_device)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (!out && c->n_total) return fail(c, PBF_ERR_INVALID_ARG, "out is NULL");
+    return read_by_id(c, c->b.x[c->cur], out, on_device, 0, c->n_total);
+}
+
+pbf_status pbf_read_velocities(pbf_ctx *c, float *out, int32_t on_device)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (!out && c->n_total) return fail(c, PBF_ERR_INVALID_ARG, "out is NULL");
+    return read_by_id(c, c->b.v[c->cur], out, on_device, 0, c->n_total);
+}
+
+pbf_status pbf_batch_read_positions(pbf_ctx *c, int32_t scene, float *out, int32_t on_device)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (scene < 0 || scene >= c->n_scenes) return fail(c, PBF_ERR_INVALID_ARG, "bad scene index");
+    if (!out && c->params[scene].n) return fail(c, PBF_ERR_INVALID_ARG, "out is NULL");
+    return read_by_id(c, c->b.x[c->cur], out, on_device, c->pid_off[scene], c->pid_off[scene + 1]);
+}
+
+pbf_status pbf_get_counts(const pbf_ctx *c, int32_t *n_scenes, int64_t *n_total)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (n_scenes) *n_scenes = c->n_scenes;
+    if (n_total) *n_total = c->n_total;
+    return PBF_OK;
+}
+
+pbf_status pbf_set_graph(pbf_ctx *c, int32_t enable)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    c->graph = enable != 0;
+    if (!c->graph) {
+        HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+        drop_graphs(c);
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_set_block_size(pbf_ctx *c, int32_t kernel, int32_t threads)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (kernel < 0 || kernel >= K_COUNT) return fail(c, PBF_ERR_INVALID_ARG, "bad kernel index");
+    if (threads == 0) threads = kDefaultBlock[kernel];
+    if (threads < 64 || threads > 1024 || threads % 64)
+        return fail(c, PBF_ERR_INVALID_ARG, "threads must be a multiple of 64 in [64, 1024]");
+    if (fixed_shape(kernel) && threads != kDefaultBlock[kernel])
+        return fail(c, PBF_ERR_INVALID_ARG, "this kernel has a fixed launch shape");
+    if (c->ls.block[kernel] != threads) {
+        HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+        drop_graphs(c);
+        c->ls.block[kernel] = threads;
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_profile_enable(pbf_ctx *c, int32_t enable)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    c->profiling = enable != 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        c->timer.total_ms[k] = 0.0;
+        c->timer.launches[k] = 0;
+    }
+    c->timer.used = 0;
+    c->timer.status = hipSuccess;
+    return PBF_OK;
+}
+
+pbf_status pbf_profile_read(pbf_ctx *c, double *total_ms, int64_t *launches, int32_t count)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (count < 0 || count > K_COUNT || (count && (!total_ms || !launches)))
+        return fail(c, PBF_ERR_INVALID_ARG, "bad output arrays");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    for (int k = 0; k < count; ++k) {
+        total_ms[k] = c->timer.total_ms[k];
+        launches[k] = c->timer.launches[k];
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_stats(pbf_ctx *c, pbf_step_stats *o)
+{
+    if (!c || !o) return PBF_ERR_INVALID_ARG;
+    std::memset(o, 0, sizeof *o);
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    std::vector<uint32_t> ge, meta;
+    std::vector<unsigned long long> tot;
+    if ((st = d2h(c, tot, c->b.totals, 2)) != PBF_OK) return st;
+    o->total_particle_iterations = (int64_t)tot[0];
+    o->total_steps = (int64_t)tot[1];
+    if ((st = d2h(c, ge, c->b.count_ge, (size_t)PBF_MAX_ITERS + 2)) != PBF_OK) return st;
+    if ((st = d2h(c, meta, c->b.nmeta, (size_t)c->n_total)) != PBF_OK) return st;
+    o->n_iters = c->b.n_iters;
+    for (int k = 0; k < c->b.n_iters; ++k) {
+        o->active[k] = ge[k + 1];
+        o->particle_iterations += ge[k + 1];
+    }
+    for (uint32_t m : meta) {
+        int32_t cnt = (int32_t)(m & 0xffffu);
+        o->neighbour_pairs += cnt;
+        o->max_neighbours = std::max(o->max_neighbours, cnt);
+    }
+    return latched(c);
+}
+
+pbf_status pbf_debug_keys(pbf_ctx *c, uint32_t *keys)
+{
+    if (!c || (!keys && c->n_total)) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    std::vector<uint32_t> k, id;
+    std::vector<float4> x;
+    if ((st = d2h(c, k, c->b.key, (size_t)c->n_total)) != PBF_OK) return st;
+    if ((st = d2h(c, id, c->b.id[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    for (size_t s = 0; s < k.size(); ++s) {
+        // scene of the particle from its global ID
+        int32_t sc = (int32_t)(std::upper_bound(c->pid_off.begin(), c->pid_off.end(), (int64_t)id[s]) -
+                               c->pid_off.begin()) - 1;
+        keys[id[s]] = k[s] - c->scenes[sc].cell_off;
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_debug_permutation(pbf_ctx *c, int32_t *ids)
+{
+    if (!c || (!ids && c->n_total)) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    std::vector<uint32_t> id;
+    if ((st = d2h(c, id, c->b.id[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    for (size_t s = 0; s < id.size(); ++s) ids[s] = (int32_t)id[s];
+    return PBF_OK;
+}
+
+pbf_status pbf_debug_neighbours(pbf_ctx *c, int32_t *counts, int32_t *ids, int64_t cap,
+                                int64_t *total)
+{
+    if (!c || (!counts && c->n_total) || !total) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    const size_t n = (size_t)c->n_total;
+    std::vector<uint32_t> order, meta, id, nbr;
+    if ((st = d2h(c, order, c->b.order, n)) != PBF_OK) return st;
+    if ((st = d2h(c, meta, c->b.nmeta, n)) != PBF_OK) return st;
+    if ((st = d2h(c, id, c->b.id[c->cur], n)) != PBF_OK) return st;
+    std::vector<int64_t> off(n + 1, 0);
+    std::vector<uint32_t> tpos(n);  // slot -> t
+    for (size_t t = 0; t < n; ++t) tpos[order[t]] = (uint32_t)t;
+    for (size_t s = 0; s < n; ++s) counts[id[s]] = (int32_t)(meta[tpos[s]] & 0xffffu);
+    for (size_t g = 0; g < n; ++g) off[g + 1] = off[g] + counts[g];
+    *total = off[n];
+    if (!ids || cap < off[n]) return PBF_OK;
+    if ((st = d2h(c, nbr, c->b.nbr, n * (size_t)c->b.nbr_cap)) != PBF_OK) return st;
+    for (size_t s = 0; s < n; ++s) {
+        const uint32_t t = tpos[s];
+        const int32_t cnt = (int32_t)(meta[t] & 0xffffu);
+        int32_t *dst = ids + off[id[s]];
+        for (int32_t q = 0; q < cnt; ++q) dst[q] = (int32_t)id[nbr[(size_t)q * n + t]];
+        std::sort(dst, dst + cnt);
+    }
+    return PBF_OK;
+}
+
+pbf_status pbf_debug_lambda(pbf_ctx *c, float *lambda)
+{
+    if (!c || (!lambda && c->n_total)) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    std::vector<float4> xs;
+    std::vector<uint32_t> id;
+    if ((st = d2h(c, xs, (const float4 *)c->b.xs[c->b.n_iters & 1], (size_t)c->n_total)) != PBF_OK) return st;
+    if ((st = d2h(c, id, c->b.id[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    for (size_t s = 0; s < id.size(); ++s) lambda[id[s]] = xs[s].w;
+    return PBF_OK;
+}
+
+pbf_status pbf_debug_levels(pbf_ctx *c, uint8_t *levels)
+{
+    if (!c || (!levels && c->n_total)) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    std::vector<uint8_t> lv;
+    std::vector<uint32_t> id;
+    if ((st = d2h(c, lv, (const uint8_t *)c->b.lvl[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    if ((st = d2h(c, id, c->b.id[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    for (size_t s = 0; s < id.size(); ++s) levels[id[s]] = lv[s];
+    return PBF_OK;
+}
+
+pbf_status pbf_get_state(pbf_ctx *c, float *x, float *v, int64_t *step)
+{
+    if (!c || ((!x || !v) && c->n_total)) return PBF_ERR_INVALID_ARG;
+    pbf_status st = read_by_id(c, c->b.x[c->cur], x, 0, 0, c->n_total);
+    if (st != PBF_OK) return st;
+    st = read_by_id(c, c->b.v[c->cur], v, 0, 0, c->n_total);
+    if (st != PBF_OK) return st;
+    if (step) *step = c->step;
+    return PBF_OK;
+}
+
+pbf_status pbf_set_state(pbf_ctx *c, const float *x, const float *v, int64_t step)
+{
+    if (!c || ((!x || !v) && c->n_total) || step < 0) return PBF_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < c->n_total; ++i)
+        if (!finite3(x + 3 * i) || !finite3(v + 3 * i))
+            return fail(c, PBF_ERR_NONFINITE, "non-finite state");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    pbf_status st = upload_state(c, x, v);
+    if (st != PBF_OK) return st;
+    HIPCHK(c, hipMemsetAsync(c->b.err, 0, sizeof(uint32_t), c->stream), "clear faults");
+    HIPCHK(c, hipMemsetAsync(c->b.totals, 0, 2 * sizeof(unsigned long long), c->stream),
+           "clear totals");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    c->step = step;
+    c->stepped = false;
+    return PBF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bit-exact: cell keys, sort permutation, neighbour sets and levels (with the
+guard bands of tests/parity.py).  Floating point: positions within 1e-5 of
+the largest box extent after one step, lambdas within the FP32 bound
+derived in tests/parity.py / the design notes.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (first import can be slow; keep it out of test timeouts)
+
+import oracle
+import scenes
+from parity import (compare_keys, key_ambiguous, neighbour_mismatch, pos_tol, ref_csr,
+                    ulp_sensitivity)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    oracle.build(force=False)
+    from paper_1608_04721_amd import _lib
+    _lib.load()
+
+
+def _sim(sc, **kw):
+    from paper_1608_04721_amd import Sim
+    return Sim(sc, **kw)
+
+
+def _lambda_tol(lam_ref):
+    # lambda = -C/(S + eps): C carries ~1e-6 absolute FP32 error from the
+    # density sum, S + eps >= eps; 1e-4 relative covers S.
+    return 1e-6 + 1e-4 * np.abs(lam_ref)
+
+
+def _check_step(sc, sim, x_ref, v_ref, info, check_nbrs=True, nbr_sample=None, tol=None,
+                lam_extra=0.0):
+    x = sim.positions().astype(np.float64)
+    v = sim.velocities().astype(np.float64)
+    tol = pos_tol(sc) if tol is None else tol
+    ex = np.abs(x - x_ref).max() if sc.n else 0.0
+    ev = np.abs(v - v_ref).max() if sc.n else 0.0
+    assert ex <= tol, f"positions: {ex:.3e} > {tol:.1e}"
+    assert ev <= tol / float(sc.dt), f"velocities: {ev:.3e}"
+    if info is None or sc.n == 0:
+        return ex
+    xs0 = info["xs_iter"][0]
+    bad, amb = compare_keys(sc, sim.debug_keys(), info["keys"], xs0)
+    assert bad == 0, f"{bad} cell keys differ"
+    if amb == 0:
+        assert np.array_equal(sim.debug_permutation(), info["perm"])
+    assert np.array_equal(sim.debug_levels().astype(np.int32), info["levels"])
+    if check_nbrs:
+        nb = neighbour_mismatch(sc, sim.debug_neighbours(), ref_csr(info), xs0, ids=nbr_sample)
+        assert nb == 0, f"{nb} neighbour pairs differ outside the guard band"
+    lam = sim.debug_lambda().astype(np.float64)
+    lv = info["levels"]
+    lam_ref = info["lambda_iter"][lv - 1, np.arange(sc.n)]
+    assert np.all(np.abs(lam - lam_ref) <= _lambda_tol(lam_ref) + lam_extra), \
+        f"lambda max err {np.abs(lam - lam_ref).max():.3e}"
+    return ex
+
+
+def test_one_step_dam_break_4k():
+    sc = scenes.dam_break_4k()
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    assert not key_ambiguous(sc, info["xs_iter"][0]).any()
+    with _sim(sc) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info)
+        st = sim.stats()
+        assert st["particle_iterations"] == sc.n * sc.n_max
+        assert st["neighbour_pairs"] == int(info["nbr_count"].sum())
+
+
+def test_resynchronised_steps_dam_break_4k():
+    """Each of the 10 steps from the GPU's own float32 state matches one
+    oracle step from that state (per-step resynchronised parity)."""
+    sc = scenes.dam_break_4k()
+    drift = []
+    with _sim(sc) as sim:
+        x_free, v_free = sc.x0.astype(np.float64), sc.v0.astype(np.float64)
+        for step in range(sc.steps):
+            x0, v0, _ = sim.get_state()
+            x_ref, v_ref, info = oracle.apbf_step(sc, x0, v0, trace=True)
+            sim.step(1)
+            _check_step(sc, sim, x_ref, v_ref, info)
+            x_free, v_free, _ = oracle.apbf_step(sc, x_free, v_free)
+            drift.append(float(np.abs(sim.positions() - x_free).max()))
+    print("free-running drift per step:", ["%.2e" % d for d in drift])
+
+
+def test_uniform_levels_equal_oracle_plain_pbf():
+    """APBF with every N_i = n_max on the GPU against the oracle's separate
+    plain-PBF routine."""
+    sc = scenes.block(12, 10, 9, seed=21, n_min=1, n_max=6, vel_sigma=0.3)
+    x_ref, v_ref = oracle.pbf_step(sc, sc.x0, sc.v0, 6)
+    with _sim(sc) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, None)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_levels(seed):
+    sc = scenes.block(13, 9, 11, seed=seed, n_min=2, n_max=7, levels="random", vel_sigma=0.4)
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    with _sim(sc) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info)
+        st = sim.stats()
+        for k in range(sc.n_max):
+            assert st["active"][k] == int((info["levels"] > k).sum())
+
+
+def test_distance_to_camera_levels():
+    sc = scenes.block(16, 8, 16, seed=5, n_min=3, n_max=8, vel_sigma=0.2)
+    cam = np.array([0.4, 1.0, -0.8], np.float32)
+    d = np.linalg.norm(sc.x0.astype(np.float64) - cam, axis=1)
+    sc = sc.with_lod(scenes.LOD_DTC)
+    sc.camera, sc.d_near, sc.d_far = cam, np.float32(d.min()), np.float32(d.max())
+    ref_lv = oracle.levels(sc, sc.x0.astype(np.float64))
+    # bin edges: t * (n_max - n_min + 1) within 1e-5 of an integer
+    t = np.clip((d - float(sc.d_near)) / (float(sc.d_far) - float(sc.d_near)), 0, 1) * 6
+    near_edge = np.abs(t - np.round(t)) < 1e-5
+    with _sim(sc) as sim:
+        sim.step(1)
+        lv = sim.debug_levels().astype(np.int32)
+    assert np.array_equal(lv[~near_edge], ref_lv[~near_edge])
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, mode=scenes.LOD_EXPLICIT, levels=lv,
+                                          trace=True)
+    with _sim(sc.with_lod(scenes.LOD_EXPLICIT, levels=lv)) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 257, 1000])
+def test_ragged_random_clouds(n):
+    """Irregular inputs: random points with coincident duplicates, random
+    velocities, walls hit, counts around the wave and block sizes."""
+    sc = scenes.random_cloud(n, seed=n, extent=0.45, n_min=1, n_max=5)
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    sens_x, sens_l = ulp_sensitivity(sc)
+    tol = max(pos_tol(sc), 4.0 * sens_x)
+    print(f"n={n}: one-ulp spread of the oracle {sens_x:.2e}, tolerance {tol:.2e}")
+    with _sim(sc) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info, tol=tol, lam_extra=4.0 * sens_l)
+
+
+def test_single_particle_ballistic():
+    x = np.array([[0.5, 0.9, 0.4]], np.float32)
+    v = np.array([[0.3, -0.2, 0.1]], np.float32)
+    sc = scenes.Scene(name="one", x0=x, v0=v, lo=(0, 0, 0), hi=(1, 1, 1), n_min=3, n_max=3)
+    x_ref, v_ref = oracle.run(sc, steps=5)
+    with _sim(sc) as sim:
+        sim.step(5)
+        assert np.abs(sim.positions() - x_ref).max() <= pos_tol(sc)
+
+
+def test_empty_scene():
+    sc = scenes.Scene(name="empty", x0=np.zeros((0, 3)), v0=np.zeros((0, 3)), lo=(0, 0, 0),
+                      hi=(1, 1, 1), n_min=1, n_max=2)
+    with _sim(sc) as sim:
+        sim.step(3)
+        sim.sync()
+        assert sim.positions().shape == (0, 3)
+
+
+def test_batch_equals_serial_and_oracle():
+    """Scenes of uneven sizes and iteration ranges in one context: each scene
+    is bit-identical to its own context, and matches the oracle."""
+    scs = [scenes.block(7, 5, 6, seed=1, n_min=2, n_max=4, levels="random", vel_sigma=0.2),
+           scenes.block(10, 12, 9, seed=2, n_min=3, n_max=9, levels="random", vel_sigma=0.5),
+           scenes.random_cloud(333, seed=3, extent=0.4, n_min=1, n_max=3),
+           scenes.block(4, 4, 4, seed=4, n_min=6, n_max=6)]
+    with _sim(scs) as batch:
+        batch.step(3)
+        xb = [batch.scene_positions(i) for i in range(len(scs))]
+        assert np.array_equal(np.concatenate(xb), batch.positions())
+    for i, sc in enumerate(scs):
+        with _sim(sc) as one:
+            one.step(3)
+            assert np.array_equal(one.positions(), xb[i]), f"scene {i} differs from serial"
+    with _sim(scs) as batch:
+        batch.step(1)
+        for i, sc in enumerate(scs):
+            x_ref, _, _ = oracle.apbf_step(sc, sc.x0, sc.v0)
+            tol = max(pos_tol(sc), 4.0 * ulp_sensitivity(sc)[0])
+            assert np.abs(batch.scene_positions(i) - x_ref).max() <= tol, i
+
+
+def test_graph_replay_equals_direct_launch():
+    sc = scenes.block(14, 10, 12, seed=9, n_min=2, n_max=6, levels="random", vel_sigma=0.3)
+    with _sim(sc) as a, _sim(sc) as b:
+        b.set_graph(True)
+        for _ in range(4):  # replays of both parity graphs, with host reads between
+            a.step(1)
+            b.step(1)
+            assert np.array_equal(a.positions(), b.positions())
+            assert np.array_equal(a.velocities(), b.velocities())
+
+
+def test_two_runs_bit_identical():
+    sc = scenes.block(15, 11, 13, seed=12, n_min=2, n_max=8, levels="random", vel_sigma=0.5)
+    out = []
+    for _ in range(2):
+        with _sim(sc) as s:
+            s.step(6)
+            out.append((s.positions(), s.velocities()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_resume_from_saved_state_bit_identical():
+    sc = scenes.block(12, 12, 12, seed=13, n_min=2, n_max=6, levels="random", vel_sigma=0.3)
+    with _sim(sc) as a:
+        a.step(3)
+        x, v, step = a.get_state()
+        assert step == 3
+        a.step(4)
+        xa = a.positions()
+    with _sim(sc) as b:
+        b.set_state(x, v, step)
+        b.step(4)
+        assert np.array_equal(b.positions(), xa)
+
+
+def test_neighbour_capacity_fault_is_reported():
+    """A capacity below the real neighbour counts (set from the host) is
+    latched on the device and reported at the next synchronising call."""
+    from paper_1608_04721_amd import PbfError
+    from paper_1608_04721_amd._lib import PBF_ERR_CAPACITY
+    sc = scenes.block(8, 8, 8, seed=1, n_min=1, n_max=2)
+    with _sim(sc, max_neighbours=8) as sim:
+        sim.step(1)
+        with pytest.raises(PbfError) as e:
+            sim.sync()
+        assert e.value.status == PBF_ERR_CAPACITY
+
+
+def test_invalid_levels_rejected():
+    from paper_1608_04721_amd import PbfError, PBF_LOD_EXPLICIT
+    sc = scenes.block(4, 4, 4, n_min=2, n_max=4)
+    with _sim(sc) as sim:
+        with pytest.raises(PbfError):
+            sim.set_lod(PBF_LOD_EXPLICIT, levels=np.full(sc.n, 5, np.uint8))
+        with pytest.raises(PbfError):
+            sim.set_lod(scenes.LOD_DTC, camera=(0, 0, 0), d_near=1.0, d_far=1.0)
+
+
+@pytest.mark.parametrize("name", ["dam_break_262k", "tank_1m"])
+def test_full_size_one_step(name):
+    """Full-size workloads in the benchmark's launch configuration (graph
+    replay): every particle's position after one step, every key, the levels
+    and a sample of neighbour sets against the oracle."""
+    sc = scenes.CONFIGS[name]()
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    rng = np.random.default_rng(0)
+    sample = rng.choice(sc.n, size=3000, replace=False)
+    with _sim(sc) as sim:
+        sim.set_graph(True)
+        sim.step(1)
+        sim.sync()
+        err = _check_step(sc, sim, x_ref, v_ref, info, nbr_sample=sample)
+        print(f"{name}: max position error {err:.3e} (tolerance {pos_tol(sc):.1e})")
