@@ -36,7 +36,9 @@
  *     clamped into the grid; ties in the counting sort keep particle-ID
  *     order (a stable counting sort of the particles listed by ID).
  *   - Distance-to-camera levels: t = clamp((d - d_near)/(d_far - d_near)),
- *     N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max).
+ *     N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max), decided
+ *     in float32 like the kernel (an integer chosen by floating point is
+ *     chosen in the same precision on both sides); everything else is FP64.
  * Neighbour sums run in ascending particle-ID order, so results do not
  * depend on any storage order.
  */
@@ -297,14 +299,22 @@ int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t
         } else if (lod->mode == 1) {
             L = lod->levels[i];
         } else {
+            /* The level is an integer decided by floating point, so it is
+             * decided in the kernel's precision: float32, one rounding per
+             * operation (no contraction), correctly rounded sqrt and division,
+             * in this order. */
             const double *xi = x + 3 * (int64_t)i;
-            double dx = xi[0] - lod->camera[0], dy = xi[1] - lod->camera[1],
-                   dz = xi[2] - lod->camera[2];
-            double d = sqrt(dx * dx + dy * dy + dz * dz);
-            double t = (d - lod->d_near) / (lod->d_far - lod->d_near);
-            if (t < 0.0) t = 0.0;
-            if (t > 1.0) t = 1.0;
-            L = p->n_max - (int32_t)floor(t * (double)(p->n_max - p->n_min + 1));
+            float dx = (float)xi[0] - (float)lod->camera[0];
+            float dy = (float)xi[1] - (float)lod->camera[1];
+            float dz = (float)xi[2] - (float)lod->camera[2];
+            float d2 = dx * dx;
+            d2 = d2 + dy * dy;
+            d2 = d2 + dz * dz;
+            float d = sqrtf(d2);
+            float t = (d - (float)lod->d_near) / ((float)lod->d_far - (float)lod->d_near);
+            if (t < 0.0f) t = 0.0f;
+            if (t > 1.0f) t = 1.0f;
+            L = p->n_max - (int32_t)floorf(t * (float)(p->n_max - p->n_min + 1));
             if (L < p->n_min) L = p->n_min;
             if (L > p->n_max) L = p->n_max;
         }

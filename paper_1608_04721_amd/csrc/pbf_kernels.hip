@@ -70,6 +70,25 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi)
     return fminf(fmaxf(v, lo), hi);
 }
 
+// Distance-to-camera level (linear map of the distance to the level range,
+// Section 4.1).  The level is an integer chosen by floating point, so the
+// operations are fixed: float32, no contraction into FMAs, correctly rounded
+// square root and division, in this order.
+__device__ __forceinline__ int dtc_level(float x, float y, float z, float cx, float cy, float cz,
+                                         float d_near, float d_far, int nmin, int nmax)
+{
+#pragma clang fp contract(off)
+    const float dx = x - cx, dy = y - cy, dz = z - cz;
+    float d2 = dx * dx;
+    d2 = d2 + dy * dy;
+    d2 = d2 + dz * dz;
+    const float d = sqrtf(d2);
+    float t = (d - d_near) / (d_far - d_near);
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    const int L = nmax - (int)floorf(t * (float)(nmax - nmin + 1));
+    return min(max(L, nmin), nmax);
+}
+
 // ------------------------------------------------------------------ fill
 __global__ void k_fill(uint32_t *__restrict__ p, uint32_t n, uint32_t value)
 {
@@ -97,11 +116,8 @@ __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
     if (S.lod_mode == PBF_LOD_EXPLICIT) {
         L = lev_by_id[id[s]];
     } else if (S.lod_mode == PBF_LOD_DTC) {
-        float dx = xi.x - S.cam[0], dy = xi.y - S.cam[1], dz = xi.z - S.cam[2];
-        float d = sqrtf(dx * dx + dy * dy + dz * dz);
-        float t = clampf((d - S.d_near) / (S.d_far - S.d_near), 0.f, 1.f);
-        L = nmax - (int)floorf(t * (float)(nmax - nmin + 1));
-        L = min(max(L, nmin), nmax);
+        L = dtc_level(xi.x, xi.y, xi.z, S.cam[0], S.cam[1], S.cam[2], S.d_near, S.d_far, nmin,
+                      nmax);
     } else {
         L = nmax;
     }
