@@ -62,8 +62,10 @@ typedef enum {
     PBF_ERR_NONFINITE = -2,     /* NaN/Inf in inputs, or positions became non-finite */
     PBF_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed */
     PBF_ERR_DEVICE = -4,        /* a HIP call failed (message in pbf_last_error) */
-    PBF_ERR_CAPACITY = -5       /* a particle exceeded the neighbour capacity, or a
-                                   grid cell held more than PBF_MAX_CELL particles */
+    PBF_ERR_CAPACITY = -5       /* a particle exceeded the neighbour capacity, a grid
+                                   cell held more than PBF_MAX_CELL particles, or a
+                                   tile too dense for on-chip staging held more than
+                                   1024 particles in six cells of a grid row */
 } pbf_status;
 
 #define PBF_MAX_ITERS 32          /* largest iteration count / level */
@@ -204,6 +206,25 @@ pbf_status pbf_debug_levels(pbf_ctx *ctx, uint8_t *levels);
  * context continues bit-identically to one that never stopped. */
 pbf_status pbf_get_state(pbf_ctx *ctx, float *x, float *v, int64_t *step);
 pbf_status pbf_set_state(pbf_ctx *ctx, const float *x, const float *v, int64_t step);
+
+/* ---------------- differentiable rollout (training form) ---------------- */
+
+/* Advance every scene by n_steps >= 1 steps like pbf_step, keeping a device
+ * copy of the state (x, v) before steps 0, ckpt_every, 2 ckpt_every, ...
+ * (ckpt_every >= 1), for a later pbf_rollout_backward.  Direct launches. */
+pbf_status pbf_rollout_forward(pbf_ctx *ctx, int32_t n_steps, int32_t ckpt_every);
+
+/* Reverse mode of the last pbf_rollout_forward (no step or state change in
+ * between): dl_dx, dl_dv = dL/dx_T and dL/dv_T of the final state, float[3
+ * n_total] in ID order; dl_dx0, dl_dv0 receive dL/dx_0 and dL/dv_0 of the
+ * state at the start of the rollout.  Each step is differentiated with its
+ * levels, neighbour sets and wall contacts held fixed (the adjoint of
+ * Eqs. 4-7 and of Fig. 7's prediction and update); every segment between
+ * checkpoints is recomputed from its checkpoint.  All four buffers are host
+ * memory (on_device = 0, synchronises) or device memory (1).  The context
+ * is left at the final state of the rollout, stored in ID order. */
+pbf_status pbf_rollout_backward(pbf_ctx *ctx, const float *dl_dx, const float *dl_dv,
+                                float *dl_dx0, float *dl_dv0, int32_t on_device);
 
 #ifdef __cplusplus
 }

@@ -78,6 +78,8 @@ def lib():
         L.orc_pbf_step.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p]
         L.orc_density.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_apbf_step_fixed.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_levels.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod), ctypes.c_void_p,
                                  ctypes.c_void_p]
         L.orc_cell_keys.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
@@ -250,4 +252,43 @@ def run(scene, steps=None, x=None, v=None, mode=None, levels=None):
     v = scene.v0.astype(np.float64) if v is None else v
     for _ in range(scene.steps if steps is None else steps):
         x, v, _ = apbf_step(scene, x, v, mode=mode, levels=levels)
+    return x, v
+
+
+def apbf_step_fixed(scene, x, v, levels, nbr_off, nbr_ids):
+    """One step with the given levels and neighbour sets (CSR by particle ID)
+    held fixed; returns float64 (x, v)."""
+    p = params(scene)
+    x = np.array(x, np.float64, order="C").reshape(-1, 3)
+    v = np.array(v, np.float64, order="C").reshape(-1, 3)
+    lv = np.ascontiguousarray(levels, np.int32)
+    off = np.ascontiguousarray(nbr_off, np.int64)
+    ids = np.ascontiguousarray(nbr_ids, np.int32)
+    if ids.size == 0:
+        ids = np.zeros(1, np.int32)
+    rc = lib().orc_apbf_step_fixed(ctypes.byref(p), lv.ctypes.data, off.ctypes.data,
+                                   ids.ctypes.data, x.ctypes.data, v.ctypes.data)
+    if rc != ORC_OK:
+        raise ValueError(f"orc_apbf_step_fixed failed ({rc})")
+    return x, v
+
+
+def rollout_structure(scene, x, v, steps):
+    """Run `steps` steps and record each step's levels and neighbour sets
+    (the discrete structure an adjoint holds fixed); returns the final
+    float64 state and the list of (levels, off, ids)."""
+    x = np.asarray(x, np.float64)
+    v = np.asarray(v, np.float64)
+    frozen = []
+    for _ in range(steps):
+        x1, v1, info = apbf_step(scene, x, v, trace=True)
+        frozen.append((info["levels"], info["nbr_off"], info["nbr_ids"]))
+        x, v = x1, v1
+    return x, v, frozen
+
+
+def rollout_fixed(scene, x, v, frozen):
+    """Replay a rollout with recorded structure (see rollout_structure)."""
+    for lv, off, ids in frozen:
+        x, v = apbf_step_fixed(scene, x, v, lv, off, ids)
     return x, v

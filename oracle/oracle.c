@@ -434,6 +434,58 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
+/* one APBF step with given neighbour sets and levels                  */
+/* ------------------------------------------------------------------ */
+
+/* The step of Fig. 7 with the discrete structure held fixed: levels
+ * lev[n] and neighbour sets as CSR (off[n+1], ids, particle-ID order)
+ * are inputs instead of being found.  With them fixed the step is a smooth
+ * function of (x, v) away from wall contacts; its finite differences are
+ * what an adjoint that keeps the neighbour sets constant differentiates. */
+int orc_apbf_step_fixed(const orc_params *p, const int32_t *lev, const int64_t *off,
+                        const int32_t *ids, double *x, double *v)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int32_t n = p->n;
+    const int32_t K = p->n_max;
+    size_t n3 = (size_t)n * 3;
+    double *xs = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+    double *dp = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+    double *lam = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    if (!xs || !dp || !lam) { rc = ORC_ERR_MEM; goto done; }
+    for (int32_t i = 0; i < n; ++i) {
+        if (lev[i] < p->n_min || lev[i] > p->n_max) { rc = ORC_ERR_ARG; goto done; }
+        for (int d = 0; d < 3; ++d) {
+            v[3 * (int64_t)i + d] += p->dt * p->g[d];
+            xs[3 * (int64_t)i + d] = x[3 * (int64_t)i + d] + p->dt * v[3 * (int64_t)i + d];
+        }
+        clamp_box(p, xs + 3 * (int64_t)i);
+    }
+    for (int32_t k = 0; k < K; ++k) {
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i)
+            if (lev[i] > k) lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i)
+            if (lev[i] > k) delta_p_of(p, xs, lam, i, ids + off[i], off[i + 1] - off[i], dp + 3 * (int64_t)i);
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i)
+            if (lev[i] > k) {
+                for (int d = 0; d < 3; ++d) xs[3 * (int64_t)i + d] += dp[3 * (int64_t)i + d];
+                clamp_box(p, xs + 3 * (int64_t)i);
+            }
+    }
+    for (size_t e = 0; e < n3; ++e) {
+        v[e] = (xs[e] - x[e]) / p->dt;
+        x[e] = xs[e];
+    }
+done:
+    free(xs); free(dp); free(lam);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* one plain PBF step, its own loop without gating                     */
 /* ------------------------------------------------------------------ */
 

@@ -15,7 +15,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libpbf.so"
-SOURCES = [CSRC / "pbf_kernels.hip", CSRC / "pbf_api.hip"]
+SOURCES = [CSRC / "pbf_kernels.hip", CSRC / "pbf_adjoint.hip", CSRC / "pbf_api.hip"]
 ARCH = "gfx950"
 
 

@@ -92,6 +92,10 @@ struct pbf_ctx {
     float *staging = nullptr;  // float[3 n_total], device
     std::vector<void *> allocs;
     std::string err;
+    // differentiable rollout: checkpoints of (x, v) in ID order, float[3 n] each
+    std::vector<float *> ckpt;  // x0, v0, x1, v1, ... (pairs)
+    int32_t roll_steps = 0, roll_every = 0;
+    bool roll_valid = false;
 };
 
 namespace {
@@ -159,7 +163,7 @@ pbf_status check_params(const pbf_params &p, int32_t idx, std::string &msg, int3
 }
 
 SceneDev make_scene(const pbf_params &p, const int32_t dims[3], uint32_t cell_off,
-                    uint32_t pid_off)
+                    uint32_t tile_off, uint32_t pid_off)
 {
     SceneDev s{};
     const double h = p.h, pi = 3.14159265358979323846;
@@ -168,6 +172,7 @@ SceneDev make_scene(const pbf_params &p, const int32_t dims[3], uint32_t cell_of
         s.hi[d] = p.box_hi[d];
         s.g[d] = p.gravity[d];
         s.dims[d] = dims[d];
+        s.tiles[d] = (dims[d] + kTileEdge - 1) / kTileEdge;
         s.cam[d] = 0.f;
     }
     s.h = p.h;
@@ -181,6 +186,7 @@ SceneDev make_scene(const pbf_params &p, const int32_t dims[3], uint32_t cell_of
     s.dt = p.dt;
     s.inv_dt = (float)(1.0 / (double)p.dt);
     s.cell_off = cell_off;
+    s.tile_off = tile_off;
     s.pid_off = pid_off;
     s.n_min = p.n_min;
     s.n_max = p.n_max;
@@ -217,6 +223,14 @@ bool fixed_shape(int k)
            k == K_LEVEL_SCAN || k == K_LEVEL_SCATTER;
 }
 
+// tile kernels are compiled for a bounded block size
+int max_block(int k)
+{
+    if (k == K_NEIGHBOURS) return kNbrThreads;
+    if (k == K_LAMBDA || k == K_UPDATE) return kTileThreads;
+    return 1024;
+}
+
 pbf_status latched(pbf_ctx *c)
 {
     uint32_t e = 0;
@@ -227,7 +241,8 @@ pbf_status latched(pbf_ctx *c)
     if (e & ERR_NEIGHBOUR_CAP)
         return fail(c, PBF_ERR_CAPACITY, "a particle exceeded the neighbour capacity");
     if (e & ERR_CELL_CAP)
-        return fail(c, PBF_ERR_CAPACITY, "a grid cell held more than PBF_MAX_CELL particles");
+        return fail(c, PBF_ERR_CAPACITY, "a grid cell held more than PBF_MAX_CELL particles, or "
+                                          "six cells of a grid row more than 1024");
     return PBF_OK;
 }
 
@@ -303,6 +318,8 @@ pbf_status d2h(pbf_ctx *c, std::vector<T> &dst, const T *src, size_t count)
     return PBF_OK;
 }
 
+pbf_status step_n(pbf_ctx *c, int32_t n_steps);
+
 pbf_status need_step(pbf_ctx *c)
 {
     if (!c->stepped) return fail(c, PBF_ERR_INVALID_ARG, "no step has run since the state was set");
@@ -348,6 +365,7 @@ void pbf_destroy(pbf_ctx *c)
         (void)hipEventDestroy(r.b);
     }
     for (void *p : c->allocs) (void)hipFree(p);
+    for (float *p : c->ckpt) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -361,18 +379,22 @@ pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const fl
     if (n_scenes < 1 || n_scenes > PBF_MAX_SCENES || !params) return PBF_ERR_INVALID_ARG;
     // ---- host-side checks, before any HIP call
     std::vector<std::array<int32_t, 3>> dims((size_t)n_scenes);
-    int64_t n_total = 0, cells = 0;
+    int64_t n_total = 0, cells = 0, tiles = 0;
     int32_t cap = 0, kmax = 1;
     std::string msg;
     for (int32_t s = 0; s < n_scenes; ++s) {
         if (check_params(params[s], s, msg, dims[s].data()) != PBF_OK) return PBF_ERR_INVALID_ARG;
         n_total += params[s].n;
         cells += (int64_t)dims[s][0] * dims[s][1] * dims[s][2];
+        tiles += (int64_t)((dims[s][0] + kTileEdge - 1) / kTileEdge) *
+                 ((dims[s][1] + kTileEdge - 1) / kTileEdge) *
+                 ((dims[s][2] + kTileEdge - 1) / kTileEdge);
         cap = std::max(cap, params[s].max_neighbours ? params[s].max_neighbours
                                                      : PBF_DEFAULT_NEIGHBOURS);
         kmax = std::max(kmax, params[s].n_max);
     }
-    if (n_total >= ((int64_t)1 << 31) || cells >= ((int64_t)1 << 32) - 2)
+    if (n_total >= ((int64_t)1 << 31) || cells >= ((int64_t)1 << 32) - 2 ||
+        tiles >= ((int64_t)1 << 31))
         return PBF_ERR_INVALID_ARG;
     if (n_total > 0 && (!x0 || !v0)) return PBF_ERR_INVALID_ARG;
 
@@ -412,22 +434,34 @@ pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const fl
         c->own_stream = true;
     }
 
-    uint32_t coff = 0;
+    uint32_t coff = 0, toff = 0;
+    std::vector<uint32_t> tile_scene((size_t)tiles), id_scene((size_t)n_total);
+    for (int32_t s = 0; s < n_scenes; ++s)
+        for (int64_t g = c->pid_off[s]; g < c->pid_off[s + 1]; ++g) id_scene[g] = (uint32_t)s;
     for (int32_t s = 0; s < n_scenes; ++s) {
-        c->scenes.push_back(make_scene(params[s], dims[s].data(), coff, (uint32_t)c->pid_off[s]));
+        c->scenes.push_back(make_scene(params[s], dims[s].data(), coff, toff,
+                                       (uint32_t)c->pid_off[s]));
+        const SceneDev &sd = c->scenes.back();
+        const uint32_t nt = (uint32_t)sd.tiles[0] * (uint32_t)sd.tiles[1] * (uint32_t)sd.tiles[2];
+        for (uint32_t t = 0; t < nt; ++t) tile_scene[toff + t] = (uint32_t)s;
         coff += (uint32_t)((int64_t)dims[s][0] * dims[s][1] * dims[s][2]);
+        toff += nt;
     }
 
     StepBuffers &b = c->b;
     const size_t n = (size_t)n_total;
     b.n = n_total;
     b.n_cells = (uint32_t)cells;
+    b.n_tiles = (uint32_t)tiles;
     b.n_iters = kmax;
     b.nbr_cap = cap;
-    b.n_level_blocks = (int32_t)((n_total + kLevelBlock - 1) / kLevelBlock);
-    b.n_scan_blocks = (int32_t)((cells + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems));
+    b.nbr_stride = (cap + 7) / 8 * 8;
+    b.n_level_blocks = (int32_t)((tiles + kLevelBlock - 1) / kLevelBlock);
+    b.n_scan_blocks = (int32_t)((std::max(cells, tiles) + kScanBlock * kScanItems - 1) /
+                                (kScanBlock * kScanItems));
     SceneDev *dsc = nullptr;
     uint8_t *dlev = nullptr;
+    uint32_t *dtile_scene = nullptr, *did_scene = nullptr;
     hipError_t e = hipSuccess;
 #define AL(P, N) if (e == hipSuccess) e = dalloc(c, &(P), (N))
     AL(dsc, (size_t)n_scenes);
@@ -448,19 +482,32 @@ pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const fl
     AL(b.cell_count, (size_t)cells);
     AL(b.cell_start, (size_t)cells + 1);
     AL(b.scan_part, (size_t)b.n_scan_blocks);
-    AL(b.level_counts, (size_t)b.n_level_blocks * kmax);
-    AL(b.count_ge, (size_t)PBF_MAX_ITERS + 2);
-    AL(b.order, n);
-    AL(b.nbr, n * (size_t)cap);
-    AL(b.nmeta, n);
+    AL(dtile_scene, (size_t)tiles);
+    AL(did_scene, n);
+    AL(b.tile_count, (size_t)tiles);
+    AL(b.tile_start, (size_t)tiles + 1);
+    AL(b.tile_lvl, (size_t)tiles);
+    AL(b.level_counts, (size_t)b.n_level_blocks * (kmax + 1));
+    AL(b.tile_ge, (size_t)PBF_MAX_ITERS + 2);
+    AL(b.tile_order, (size_t)tiles);
+    AL(b.tile_rows, (size_t)tiles * kRowWords);
+    AL(b.nbr, n * (size_t)(b.nbr_stride / 8));
+    AL(b.pmeta, n);
+    AL(b.pslot, n);
     AL(b.err, 1);
     AL(b.totals, 2);
+    AL(b.level_part, (n + 63) / 64);
     AL(c->staging, n * 3);
 #undef AL
     if (e != hipSuccess) return bail(hip_fail(c, e, "allocate") );
     b.scenes = dsc;
     b.lev_by_id = dlev;
+    b.tile_scene = dtile_scene;
+    b.id_scene = did_scene;
     if (hipMemcpy(dsc, c->scenes.data(), sizeof(SceneDev) * n_scenes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(did_scene, id_scene.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dtile_scene, tile_scene.data(), sizeof(uint32_t) * tile_scene.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(b.err, 0, sizeof(uint32_t)) != hipSuccess ||
         hipMemset(b.totals, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(dlev, 0, n ? n : 1) != hipSuccess)
@@ -521,6 +568,15 @@ pbf_status pbf_step(pbf_ctx *c, int32_t n_steps)
 {
     if (!c) return PBF_ERR_INVALID_ARG;
     if (n_steps < 0) return fail(c, PBF_ERR_INVALID_ARG, "n_steps < 0");
+    if (n_steps > 0) c->roll_valid = false;
+    return step_n(c, n_steps);
+}
+
+}  // extern "C"
+
+namespace {
+pbf_status step_n(pbf_ctx *c, int32_t n_steps)
+{
     for (int32_t k = 0; k < n_steps; ++k) {
         if (c->graph && !c->profiling && c->n_total > 0) {
             hipGraphExec_t &g = c->exec[c->cur];
@@ -554,6 +610,9 @@ pbf_status pbf_step(pbf_ctx *c, int32_t n_steps)
     }
     return PBF_OK;
 }
+}  // namespace
+
+extern "C" {
 
 pbf_status pbf_sync(pbf_ctx *c)
 {
@@ -608,8 +667,9 @@ pbf_status pbf_set_block_size(pbf_ctx *c, int32_t kernel, int32_t threads)
     if (!c) return PBF_ERR_INVALID_ARG;
     if (kernel < 0 || kernel >= K_COUNT) return fail(c, PBF_ERR_INVALID_ARG, "bad kernel index");
     if (threads == 0) threads = kDefaultBlock[kernel];
-    if (threads < 64 || threads > 1024 || threads % 64)
-        return fail(c, PBF_ERR_INVALID_ARG, "threads must be a multiple of 64 in [64, 1024]");
+    if (threads < 64 || threads > max_block(kernel) || threads % 64)
+        return fail(c, PBF_ERR_INVALID_ARG, "threads must be a multiple of 64 in [64, 1024] "
+                                            "(at most 256 for neighbours, 512 for lambda/update)");
     if (fixed_shape(kernel) && threads != kDefaultBlock[kernel])
         return fail(c, PBF_ERR_INVALID_ARG, "this kernel has a fixed launch shape");
     if (c->ls.block[kernel] != threads) {
@@ -652,20 +712,21 @@ pbf_status pbf_stats(pbf_ctx *c, pbf_step_stats *o)
     std::memset(o, 0, sizeof *o);
     pbf_status st = need_step(c);
     if (st != PBF_OK) return st;
-    std::vector<uint32_t> ge, meta;
+    std::vector<uint32_t> meta;
+    std::vector<uint8_t> lv;
     std::vector<unsigned long long> tot;
     if ((st = d2h(c, tot, c->b.totals, 2)) != PBF_OK) return st;
     o->total_particle_iterations = (int64_t)tot[0];
     o->total_steps = (int64_t)tot[1];
-    if ((st = d2h(c, ge, c->b.count_ge, (size_t)PBF_MAX_ITERS + 2)) != PBF_OK) return st;
-    if ((st = d2h(c, meta, c->b.nmeta, (size_t)c->n_total)) != PBF_OK) return st;
+    if ((st = d2h(c, lv, (const uint8_t *)c->b.lvl[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    if ((st = d2h(c, meta, c->b.pmeta, (size_t)c->n_total)) != PBF_OK) return st;
     o->n_iters = c->b.n_iters;
-    for (int k = 0; k < c->b.n_iters; ++k) {
-        o->active[k] = ge[k + 1];
-        o->particle_iterations += ge[k + 1];
+    for (uint8_t L : lv) {
+        for (int k = 0; k < (int)L && k < PBF_MAX_ITERS; ++k) o->active[k] += 1;
+        o->particle_iterations += L;
     }
     for (uint32_t m : meta) {
-        int32_t cnt = (int32_t)(m & 0xffffu);
+        int32_t cnt = (int32_t)(m & kMetaCount);
         o->neighbour_pairs += cnt;
         o->max_neighbours = std::max(o->max_neighbours, cnt);
     }
@@ -708,24 +769,50 @@ pbf_status pbf_debug_neighbours(pbf_ctx *c, int32_t *counts, int32_t *ids, int64
     pbf_status st = need_step(c);
     if (st != PBF_OK) return st;
     const size_t n = (size_t)c->n_total;
-    std::vector<uint32_t> order, meta, id, nbr;
-    if ((st = d2h(c, order, c->b.order, n)) != PBF_OK) return st;
-    if ((st = d2h(c, meta, c->b.nmeta, n)) != PBF_OK) return st;
+    std::vector<uint32_t> meta, slot, id;
+    if ((st = d2h(c, meta, c->b.pmeta, n)) != PBF_OK) return st;
+    if ((st = d2h(c, slot, c->b.pslot, n)) != PBF_OK) return st;
     if ((st = d2h(c, id, c->b.id[c->cur], n)) != PBF_OK) return st;
     std::vector<int64_t> off(n + 1, 0);
-    std::vector<uint32_t> tpos(n);  // slot -> t
-    for (size_t t = 0; t < n; ++t) tpos[order[t]] = (uint32_t)t;
-    for (size_t s = 0; s < n; ++s) counts[id[s]] = (int32_t)(meta[tpos[s]] & 0xffffu);
+    for (size_t p = 0; p < n; ++p) counts[id[slot[p]]] = (int32_t)(meta[p] & kMetaCount);
     for (size_t g = 0; g < n; ++g) off[g + 1] = off[g] + counts[g];
     *total = off[n];
-    if (!ids || cap < off[n]) return PBF_OK;
-    if ((st = d2h(c, nbr, c->b.nbr, n * (size_t)c->b.nbr_cap)) != PBF_OK) return st;
-    for (size_t s = 0; s < n; ++s) {
-        const uint32_t t = tpos[s];
-        const int32_t cnt = (int32_t)(meta[t] & 0xffffu);
-        int32_t *dst = ids + off[id[s]];
-        for (int32_t q = 0; q < cnt; ++q) dst[q] = (int32_t)id[nbr[(size_t)q * n + t]];
-        std::sort(dst, dst + cnt);
+    if (!ids || cap < off[n] || n == 0) return PBF_OK;
+    // decode the codes with each tile's saved tables (host side)
+    const size_t T = c->b.n_tiles, stride = (size_t)c->b.nbr_stride;
+    std::vector<uint32_t> tstart, tcount, rows;
+    std::vector<uint16_t> codes;
+    if ((st = d2h(c, tstart, c->b.tile_start, T + 1)) != PBF_OK) return st;
+    if ((st = d2h(c, tcount, c->b.tile_count, T)) != PBF_OK) return st;
+    if ((st = d2h(c, rows, c->b.tile_rows, T * (size_t)kRowWords)) != PBF_OK) return st;
+    if ((st = d2h(c, codes, (const uint16_t *)c->b.nbr, n * stride)) != PBF_OK) return st;
+    // group g of particle p holds codes 8g..8g+7 at u16 offset 8 (g n + p)
+    auto code_at = [&](size_t p, int32_t q) -> uint32_t {
+        return codes[8 * ((size_t)(q / 8) * n + p) + (size_t)(q % 8)];
+    };
+    for (size_t t = 0; t < T; ++t) {
+        const uint32_t *bnd = rows.data() + t * (size_t)kRowWords;  // [row][x], then LDS bases
+        const uint32_t *base = bnd + kBndWords;
+        const bool fits = base[kStageRows] <= (uint32_t)kStageCap;
+        for (uint32_t pl = 0; pl < tcount[t]; ++pl) {
+            const size_t p = (size_t)tstart[t] + pl;
+            const int32_t cnt = (int32_t)(meta[p] & kMetaCount);
+            int32_t *dst = ids + off[id[slot[p]]];
+            for (int32_t q = 0; q < cnt; ++q) {
+                const uint32_t code = code_at(p, q);
+                uint32_t s;
+                if (fits) {
+                    int r = 0;
+                    while (base[r + 1] <= code) ++r;
+                    s = bnd[r * (kStageEdge + 1)] + (code - base[r]);
+                } else {
+                    s = bnd[(code >> kSegOffBits) * (kStageEdge + 1)] +
+                        (code & ((1u << kSegOffBits) - 1));
+                }
+                dst[q] = (int32_t)id[s];
+            }
+            std::sort(dst, dst + cnt);
+        }
     }
     return PBF_OK;
 }
@@ -782,7 +869,146 @@ pbf_status pbf_set_state(pbf_ctx *c, const float *x, const float *v, int64_t ste
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->step = step;
     c->stepped = false;
+    c->roll_valid = false;
     return PBF_OK;
+}
+
+pbf_status pbf_rollout_forward(pbf_ctx *c, int32_t n_steps, int32_t ckpt_every)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (n_steps < 1 || ckpt_every < 1)
+        return fail(c, PBF_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    for (float *p : c->ckpt) (void)hipFree(p);
+    c->ckpt.clear();
+    c->roll_valid = false;
+    const size_t n3 = (size_t)c->n_total * 3;
+    const int32_t nck = (n_steps + ckpt_every - 1) / ckpt_every;
+    for (int32_t k = 0; k < 2 * nck; ++k) {
+        float *p = nullptr;
+        hipError_t e = hipMalloc((void **)&p, std::max<size_t>(n3, 1) * sizeof(float));
+        if (e != hipSuccess) return hip_fail(c, e, "checkpoint buffers");
+        c->ckpt.push_back(p);
+    }
+    for (int32_t s = 0; s < n_steps; ++s) {
+        if (s % ckpt_every == 0) {
+            const int32_t k = s / ckpt_every;
+            HIPCHK(c, enqueue_unpermute(c->n_total, c->b.x[c->cur], c->b.id[c->cur], c->ckpt[2 * k],
+                                        0, (uint32_t)c->n_total, c->stream), "checkpoint x");
+            HIPCHK(c, enqueue_unpermute(c->n_total, c->b.v[c->cur], c->b.id[c->cur],
+                                        c->ckpt[2 * k + 1], 0, (uint32_t)c->n_total, c->stream),
+                   "checkpoint v");
+        }
+        pbf_status st = step_n(c, 1);
+        if (st != PBF_OK) return st;
+    }
+    c->roll_steps = n_steps;
+    c->roll_every = ckpt_every;
+    c->roll_valid = true;
+    return PBF_OK;
+}
+
+pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_dv, float *dl_dx0,
+                                float *dl_dv0, int32_t on_device)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (!c->roll_valid)
+        return fail(c, PBF_ERR_INVALID_ARG, "no rollout to reverse (pbf_rollout_forward, then no "
+                                            "other step or state change)");
+    const int64_t n = c->n_total;
+    const size_t n3 = (size_t)n * 3;
+    if (n && (!dl_dx || !dl_dv || !dl_dx0 || !dl_dv0))
+        return fail(c, PBF_ERR_INVALID_ARG, "null gradient buffer");
+    if (n == 0) return PBF_OK;
+    const int K = c->b.n_iters;
+    const int32_t T = c->roll_steps, C = c->roll_every;
+    const int32_t seg_len = std::min(C, T);
+    std::vector<void *> tmp;
+    auto alloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 1)) != hipSuccess) return nullptr;
+        tmp.push_back(p);
+        return p;
+    };
+    auto release = [&]() {
+        for (void *p : tmp) (void)hipFree(p);
+        tmp.clear();
+    };
+    // adjoint state (ID order) and the final state to restore afterwards
+    float *ax = (float *)alloc(n3 * 4), *av = (float *)alloc(n3 * 4);
+    float *fx = (float *)alloc(n3 * 4), *fv = (float *)alloc(n3 * 4);
+    AdjointScratch w{};
+    w.nslot = (uint32_t *)alloc((size_t)n * c->b.nbr_cap * 4);
+    w.zb = (float4 *)alloc((size_t)n * 16);
+    w.xb = (float4 *)alloc((size_t)n * 16);
+    w.dpb = (float4 *)alloc((size_t)n * 16);
+    w.gc = (float4 *)alloc((size_t)n * 16);
+    w.lb = (float *)alloc((size_t)n * 4);
+    w.sb = (float *)alloc((size_t)n * 4);
+    std::vector<StepRecord> recs((size_t)seg_len);
+    const size_t T_t = c->b.n_tiles;
+    bool ok = ax && av && fx && fv && w.nslot && w.zb && w.xb && w.dpb && w.gc && w.lb && w.sb;
+    for (auto &r : recs) {
+        if (!ok) break;
+        r.id = (uint32_t *)alloc((size_t)n * 4);
+        r.lvl = (uint8_t *)alloc((size_t)n);
+        r.nbr = (uint4 *)alloc((size_t)n * (c->b.nbr_stride / 8) * 16);
+        r.pmeta = (uint32_t *)alloc((size_t)n * 4);
+        r.pslot = (uint32_t *)alloc((size_t)n * 4);
+        r.tile_rows = (uint32_t *)alloc(T_t * kRowWords * 4);
+        r.tile_order = (uint32_t *)alloc(T_t * 4);
+        r.tile_start = (uint32_t *)alloc((T_t + 1) * 4);
+        r.tile_count = (uint32_t *)alloc(T_t * 4);
+        r.tile_ge = (uint32_t *)alloc((PBF_MAX_ITERS + 2) * 4);
+        ok = r.id && r.lvl && r.nbr && r.pmeta && r.pslot && r.tile_rows && r.tile_order &&
+             r.tile_start && r.tile_count && r.tile_ge;
+        for (int k = 0; k <= K && ok; ++k) ok = (r.snap[k] = (float4 *)alloc((size_t)n * 16)) != nullptr;
+    }
+    if (!ok) {
+        release();
+        return fail(c, PBF_ERR_OUT_OF_MEMORY, "rollout backward buffers");
+    }
+    hipError_t e = hipSuccess;
+    const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+#define BCHK(X, WHAT)                                  \
+    do {                                               \
+        if ((e = (X)) != hipSuccess) {                 \
+            pbf_status r_ = hip_fail(c, e, WHAT);      \
+            (void)hipStreamSynchronize(c->stream);     \
+            release();                                 \
+            return r_;                                 \
+        }                                              \
+    } while (0)
+    BCHK(hipMemcpyAsync(ax, dl_dx, n3 * 4, kin, c->stream), "gradient in");
+    BCHK(hipMemcpyAsync(av, dl_dv, n3 * 4, kin, c->stream), "gradient in");
+    BCHK(enqueue_unpermute(n, c->b.x[c->cur], c->b.id[c->cur], fx, 0, (uint32_t)n, c->stream), "save state");
+    BCHK(enqueue_unpermute(n, c->b.v[c->cur], c->b.id[c->cur], fv, 0, (uint32_t)n, c->stream), "save state");
+    const int32_t nseg = (T + C - 1) / C;
+    for (int32_t seg = nseg - 1; seg >= 0; --seg) {
+        const int32_t s0 = seg * C, s1 = std::min(s0 + C, T);
+        // recompute the segment from its checkpoint, recording every step
+        BCHK(enqueue_load_state(n, c->ckpt[2 * seg], c->ckpt[2 * seg + 1], c->b.id_scene,
+                                c->b.x[0], c->b.v[0], c->b.id[0], c->stream), "load checkpoint");
+        c->cur = 0;
+        for (int32_t j = 0; j < s1 - s0; ++j) {
+            BCHK(enqueue_step(c->b, c->cur, c->ls, c->stream, nullptr, &recs[j]), "recompute step");
+            c->cur ^= 1;
+        }
+        for (int32_t j = s1 - s0 - 1; j >= 0; --j)
+            BCHK(enqueue_adjoint_step(c->b, recs[j], ax, av, ax, av, w, c->stream), "adjoint step");
+    }
+    BCHK(hipMemcpyAsync(dl_dx0, ax, n3 * 4, kout, c->stream), "gradient out");
+    BCHK(hipMemcpyAsync(dl_dv0, av, n3 * 4, kout, c->stream), "gradient out");
+    // back to the final state of the rollout (storage order = ID order)
+    BCHK(enqueue_load_state(n, fx, fv, c->b.id_scene, c->b.x[0], c->b.v[0], c->b.id[0], c->stream),
+         "restore state");
+    c->cur = 0;
+    c->stepped = false;
+    BCHK(hipStreamSynchronize(c->stream), "stream synchronize");
+#undef BCHK
+    release();
+    return latched(c);
 }
 
 }  // extern "C"

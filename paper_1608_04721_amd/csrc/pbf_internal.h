@@ -5,6 +5,26 @@
 
 namespace pbf {
 
+constexpr int PBF_MAX_ITERS_INTERNAL = 32;  // equals PBF_MAX_ITERS of the public header
+
+// Spatial tiles: blocks of kTileEdge^3 grid cells.  A tile's workgroup stages
+// the (kTileEdge + 2)^3 cells around it -- kStageRows x-rows of
+// kStageEdge cells each -- into LDS and evaluates every pair of its own
+// particles from there.
+constexpr int kTileEdge = 4;
+constexpr int kStageEdge = kTileEdge + 2;
+constexpr int kStageRows = kStageEdge * kStageEdge;
+constexpr int kOwnRows = kTileEdge * kTileEdge;
+constexpr int kStageCap = 3072;    // float4 entries staged in LDS (48 KiB)
+constexpr int kTileThreads = 512;  // threads of a solver-pass tile workgroup (at most)
+constexpr int kNbrThreads = 256;   // threads of a neighbour-build tile workgroup (at most)
+constexpr int kBndWords = kStageRows * (kStageEdge + 1);  // cell bounds of the staged rows
+constexpr int kRowWords = kBndWords + kStageRows + 1;     // saved tables per tile
+constexpr int kSegOffBits = 10;    // fallback neighbour code: row << 10 | offset
+// pmeta bit fields: level << 16 | neighbour count
+constexpr int kMetaLevel = 16;
+constexpr uint32_t kMetaCount = 0xffffu;
+
 // Per-scene constants on the device.  Derived on the host in double and
 // rounded once to float.
 struct SceneDev {
@@ -16,7 +36,9 @@ struct SceneDev {
     float inv_rho0, eps, dt, inv_dt;
     float g[3];
     int32_t dims[3];
+    int32_t tiles[3];   // tiles per axis: ceil(dims / kTileEdge)
     uint32_t cell_off;  // first global cell index of the scene
+    uint32_t tile_off;  // first global tile index of the scene
     uint32_t pid_off;   // first global particle ID of the scene
     int32_t n_min, n_max;
     int32_t lod_mode;
@@ -39,10 +61,11 @@ enum Kernel : int {
     K_SCAN_APPLY,
     K_SORT_SCATTER,
     K_SORT_FINISH,
-    K_NEIGHBOURS,
+    K_TILE_PREPARE,
     K_LEVEL_COUNT,
     K_LEVEL_SCAN,
     K_LEVEL_SCATTER,
+    K_NEIGHBOURS,
     K_LAMBDA,
     K_UPDATE,
     K_COMMIT,
@@ -52,38 +75,50 @@ enum Kernel : int {
 extern const char *const kKernelNames[K_COUNT];
 extern const int kDefaultBlock[K_COUNT];
 
-constexpr int kLevelBlock = 256;  // slots per level-bucketing block (fixed: 4 waves)
-constexpr int kScanItems = 8;     // items per thread in the cell-count scan
+constexpr int kLevelBlock = 256;  // items per level-bucketing block (fixed: 4 waves)
+constexpr int kScanItems = 8;     // items per thread in the exclusive scans
 constexpr int kScanBlock = 256;   // threads of a scan block (2048 items)
 
 // Every buffer one step touches.  Storage ("slot") order is the cell order
-// of the last counting sort; "t" order is the level-bucketed order of the
-// active sets (descending level, then slot).
+// of the last counting sort.  Per-particle solver data ("p" order) is laid
+// out tile by tile: p = tile_start[tile] + own index inside the tile.
 struct StepBuffers {
-    int64_t n;              // particles, all scenes
-    uint32_t n_cells;       // cells, all scenes
-    int32_t n_iters;        // loop bound (largest n_max)
-    int32_t nbr_cap;        // neighbour capacity
-    int32_t n_level_blocks; // ceil(n / kLevelBlock)
-    int32_t n_scan_blocks;  // ceil(n_cells / (kScanBlock * kScanItems))
+    int64_t n;               // particles, all scenes
+    uint32_t n_cells;        // cells, all scenes
+    uint32_t n_tiles;        // tiles, all scenes
+    int32_t n_iters;         // loop bound (largest n_max)
+    int32_t nbr_cap;         // neighbour capacity
+    int32_t nbr_stride;      // codes per particle in nbr: nbr_cap rounded up to 8
+    int32_t n_level_blocks;  // ceil(n_tiles / kLevelBlock)
+    int32_t n_scan_blocks;   // scan blocks for max(n_cells, n_tiles)
     const SceneDev *scenes;
-    uint8_t *lev_by_id;        // explicit levels, global-ID order
+    uint8_t *lev_by_id;      // explicit levels, global-ID order
+    const uint32_t *tile_scene;  // scene of each tile
+    const uint32_t *id_scene;    // scene of each global particle ID
 
-    // ping-pong particle state (slot order): [0] = current, [1] = after reorder
+    // ping-pong particle state (slot order): [cur] -> reorder -> [cur ^ 1]
     float4 *x[2], *v[2];
     uint32_t *id[2];
     uint8_t *lvl[2];
-    float4 *xs[2];          // x* ping-pong inside a step; .w carries lambda
-    float4 *xs_pred;        // x* right after prediction, pre-sort order
+    float4 *xs[2];           // x* ping-pong inside a step; .w carries lambda
+    float4 *xs_pred;         // x* right after prediction, pre-sort order
     uint32_t *key_pre, *ticket, *key;
     uint32_t *tmp_src, *tmp_id;
     uint32_t *cell_count, *cell_start, *scan_part;
-    uint32_t *level_counts;  // n_iters * n_level_blocks, scanned in place
-    uint32_t *count_ge;      // [PBF_MAX_ITERS + 2]: |{i : N_i >= L}|
-    uint32_t *order;         // t -> slot
-    uint32_t *nbr;           // [nbr_cap][n] column-major, indexed by t
-    uint32_t *nmeta;         // [n] by t: (scene << 16) | |N_i|
+    // tiles
+    uint32_t *tile_count;    // own particles per tile
+    uint32_t *tile_start;    // exclusive scan of tile_count (n_tiles + 1)
+    uint8_t *tile_lvl;       // largest level among own particles (0: empty)
+    uint32_t *level_counts;  // (n_iters + 1) * n_level_blocks, scanned in place
+    uint32_t *tile_ge;       // [PBF_MAX_ITERS + 2]: tiles with level >= L
+    uint32_t *tile_order;    // tiles by descending level, ties by tile index
+    uint32_t *tile_rows;     // [n_tiles][kRowWords] stage layout of each tile
+    // per particle, p order
+    uint4 *nbr;              // [nbr_stride / 8][n] groups of eight u16 neighbour codes
+    uint32_t *pmeta;         // level << 16 | neighbour count
+    uint32_t *pslot;         // slot of particle p
     uint32_t *err;
+    uint32_t *level_part;    // per lod_predict block: sum of N_i
     unsigned long long *totals;  // [0] sum of N_i over steps, [1] steps
 };
 
@@ -91,22 +126,50 @@ struct LaunchShape {
     int block[K_COUNT];
 };
 
+// What the reverse pass needs of one forward step: its sorted IDs and
+// levels, its neighbour structure, and the positions (with the lambda used)
+// before every iteration's correction plus the final positions.
+struct StepRecord {
+    uint32_t *id;        // slot -> ID after the step's counting sort
+    uint8_t *lvl;        // level per slot
+    uint4 *nbr;
+    uint32_t *pmeta, *pslot;
+    uint32_t *tile_rows, *tile_order, *tile_start, *tile_count, *tile_ge;
+    float4 *snap[PBF_MAX_ITERS_INTERNAL + 1];  // (z^k, lambda^k) for k < K; snap[K] = z^K
+};
+
+// scratch of the reverse pass, slot order of the step being reversed
+struct AdjointScratch {
+    uint32_t *nslot;     // [nbr_cap][n] neighbour slots (decoded codes)
+    float4 *zb, *xb, *dpb, *gc;
+    float *lb, *sb;
+};
+
 struct Timer;  // per-launch profiling hook (host side)
 void timer_begin(Timer *tm, int kernel, hipStream_t s);
 void timer_end(Timer *tm, int kernel, hipStream_t s);
 
-// Enqueue one full step on stream s: LOD + predict, counting sort and
-// reorder, neighbour lists, level buckets, n_iters x (lambda, update),
-// commit.  `cur` selects which ping-pong half holds the current state; after
-// the step the current state is in half cur ^ 1.
+// Enqueue one full step on stream s: levels + prediction, counting sort and
+// reorder, tiles and their level buckets, neighbour lists, n_iters x
+// (lambda, update), commit.  `cur` selects the ping-pong half that holds the
+// current state; after the step the current state is in half cur ^ 1.
 hipError_t enqueue_step(const StepBuffers &b, int cur, const LaunchShape &ls, hipStream_t s,
-                        Timer *tm);
+                        Timer *tm, const StepRecord *rec = nullptr);
 
-}  // namespace pbf
+// Reverse of one recorded step: ID-order adjoints of the step's outputs (x',
+// v') in, of its inputs (x, v) out (in and out may alias).
+hipError_t enqueue_adjoint_step(const StepBuffers &b, const StepRecord &r, const float *ax_in,
+                                const float *av_in, float *ax_out, float *av_out,
+                                const AdjointScratch &w, hipStream_t s);
 
-namespace pbf {
+// Storage order = ID order, state from float[3n] arrays in ID order.
+hipError_t enqueue_load_state(int64_t n, const float *x3, const float *v3,
+                              const uint32_t *id_scene, float4 *x, float4 *v, uint32_t *id,
+                              hipStream_t s);
+
 // Scatter slot-ordered positions (or velocities) into ID order for the IDs
 // [id_lo, id_hi): out[3 (id - id_lo) + c].
 hipError_t enqueue_unpermute(int64_t n, const float4 *x, const uint32_t *id, float *out,
                              uint32_t id_lo, uint32_t id_hi, hipStream_t s);
+
 }  // namespace pbf

@@ -1,32 +1,44 @@
 // gfx950 kernels of one adaptive PBF step (Section 5, Fig. 7 of the paper).
 //
 // Data layout in HBM (all scenes of a context concatenated):
-//   x, v      float4[n]  slot order (cell-sorted); x.w holds the scene index bits
-//   xs[2]     float4[n]  predicted positions x*, ping-pong across solver
-//                        iterations; .w holds lambda_i
-//   id, lvl   u32/u8[n]  particle ID and level N_i per slot
-//   key       u32[n]     global cell key per slot (scene cell offset + local key)
-//   cell_start u32[G+1]  first slot of every cell (exclusive scan of counts)
-//   order     u32[n]     level buckets: t -> slot, descending N_i, ties by slot,
-//                        so the active set P_k of iteration k is order[0, |P_k|)
-//   nbr       u32[cap][n] neighbour slots, column-major by t (coalesced)
-//   nmeta     u32[n]     by t: scene << 16 | neighbour count
+//   x, v        float4[n]  slot order (cell-sorted); x.w holds the scene index bits
+//   xs[2]       float4[n]  predicted positions x*, ping-pong across solver
+//                          iterations; .w holds lambda_i
+//   id, lvl     u32/u8[n]  particle ID and level N_i per slot
+//   key         u32[n]     global cell key per slot (scene cell offset + local
+//                          key, x fastest)
+//   cell_start  u32[G+1]   first slot of every cell (exclusive scan of counts)
+//   tiles       blocks of 4^3 cells; tile_start is the exclusive scan of their
+//               particle counts, tile_order lists them by descending largest
+//               level, so the tiles holding active particles of iteration k
+//               are a prefix of tile_order (Eqs. 9-10: the active sets nest)
+//   nbr         neighbour codes in p order (p = tile_start[tile] + own index),
+//               u16 codes packed eight per 16-byte group, group-major:
+//               group g of particle p at [g * n + p]; a code is the
+//               neighbour's index in the tile's LDS stage, or row << 10 |
+//               offset when the stage does not fit in LDS
+//   pmeta/pslot u32[n]     level << 16 | neighbour count, and slot, per p
 //
-// Every kernel is gather-only (no floating-point atomics), so a step is
-// deterministic; integer atomics are used only for cell counts and tickets,
-// and the tickets are replaced by a rank by particle ID before use.
+// A tile's workgroup stages the 6^3 cells around its 4^3 cells (36 x-rows of
+// 6 cells, contiguous slot ranges) into LDS once per pass and evaluates all
+// pairs of its own particles from there.  Every sum is a gather in a fixed
+// order (no floating-point atomics), so a step is deterministic; integer
+// atomics only count cell occupancy, and the resulting tickets are replaced
+// by the rank of the particle ID inside its cell.
 #include "pbf_internal.h"
 #include "../../include/pbf.h"
 
 namespace pbf {
 
 const char *const kKernelNames[K_COUNT] = {
-    "fill",         "lod_predict",  "scan_reduce",   "scan_top",     "scan_apply",
-    "sort_scatter", "sort_finish",  "neighbours",    "level_count",  "level_scan",
-    "level_scatter", "lambda",      "update",        "commit"};
+    "fill",        "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",
+    "sort_scatter", "sort_finish", "tile_prepare", "level_count", "level_scan",
+    "level_scatter", "neighbours", "lambda",      "update",       "commit"};
 
-const int kDefaultBlock[K_COUNT] = {256, 256, kScanBlock, 1024, kScanBlock, 256, 256,
-                                    256, kLevelBlock, 1024, kLevelBlock, 256, 256, 256};
+const int kDefaultBlock[K_COUNT] = {256,         256,          kScanBlock,   1024,
+                                    kScanBlock,  256,          256,          256,
+                                    kLevelBlock, 1024,         kLevelBlock,  kNbrThreads,
+                                    kTileThreads, kTileThreads, 256};
 
 namespace {
 
@@ -57,6 +69,20 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *ld
     if (block_total) *block_total = lds[nw];
     __syncthreads();
     return r;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+    return v;
 }
 
 __device__ __forceinline__ int cell_coord(float p, float lo, float h, int dims)
@@ -100,48 +126,79 @@ __global__ void k_fill(uint32_t *__restrict__ p, uint32_t n, uint32_t value)
 // Fig. 7 first loop for every particle, plus the level N_i (Eq. 8, adaption
 // model of Section 4.1) from the position at the start of the step, the cell
 // key of x*, and a ticket inside its cell from the counting-sort histogram.
+// Lanes of a wave that share a cell take one atomic for all of them.
 __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
                               const float4 *__restrict__ x, float4 *__restrict__ v,
                               const uint32_t *__restrict__ id, const uint8_t *__restrict__ lev_by_id,
                               float4 *__restrict__ xs_pred, uint8_t *__restrict__ lvl,
                               uint32_t *__restrict__ key, uint32_t *__restrict__ ticket,
-                              uint32_t *__restrict__ cell_count)
+                              uint32_t *__restrict__ cell_count,
+                              uint32_t *__restrict__ level_part)
 {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    float4 xi = x[s];
-    const SceneDev &S = sc[__float_as_int(xi.w)];
-    const int nmin = S.n_min, nmax = S.n_max;
-    int L;
-    if (S.lod_mode == PBF_LOD_EXPLICIT) {
-        L = lev_by_id[id[s]];
-    } else if (S.lod_mode == PBF_LOD_DTC) {
-        L = dtc_level(xi.x, xi.y, xi.z, S.cam[0], S.cam[1], S.cam[2], S.d_near, S.d_far, nmin,
-                      nmax);
-    } else {
-        L = nmax;
+    __shared__ uint32_t wsum[1024 / 64];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = s < n;
+    uint32_t k = 0xffffffffu;
+    int L = 0;
+    if (valid) {
+        const float4 xi = x[s];
+        const SceneDev &S = sc[__float_as_int(xi.w)];
+        const int nmin = S.n_min, nmax = S.n_max;
+        if (S.lod_mode == PBF_LOD_EXPLICIT) {
+            L = lev_by_id[id[s]];
+        } else if (S.lod_mode == PBF_LOD_DTC) {
+            L = dtc_level(xi.x, xi.y, xi.z, S.cam[0], S.cam[1], S.cam[2], S.d_near, S.d_far,
+                          nmin, nmax);
+        } else {
+            L = nmax;
+        }
+        const float dt = S.dt;
+        float4 vi = v[s];
+        vi.x += dt * S.g[0];
+        vi.y += dt * S.g[1];
+        vi.z += dt * S.g[2];
+        const float px = clampf(xi.x + dt * vi.x, S.lo[0], S.hi[0]);
+        const float py = clampf(xi.y + dt * vi.y, S.lo[1], S.hi[1]);
+        const float pz = clampf(xi.z + dt * vi.z, S.lo[2], S.hi[2]);
+        v[s] = vi;
+        xs_pred[s] = make_float4(px, py, pz, 0.f);
+        lvl[s] = (uint8_t)L;
+        const float h = S.h;
+        const int cx = cell_coord(px, S.lo[0], h, S.dims[0]);
+        const int cy = cell_coord(py, S.lo[1], h, S.dims[1]);
+        const int cz = cell_coord(pz, S.lo[2], h, S.dims[2]);
+        k = S.cell_off + (uint32_t)(((int64_t)cz * S.dims[1] + cy) * S.dims[0] + cx);
+        key[s] = k;
     }
-    const float dt = S.dt;
-    float4 vi = v[s];
-    vi.x += dt * S.g[0];
-    vi.y += dt * S.g[1];
-    vi.z += dt * S.g[2];
-    float px = clampf(xi.x + dt * vi.x, S.lo[0], S.hi[0]);
-    float py = clampf(xi.y + dt * vi.y, S.lo[1], S.hi[1]);
-    float pz = clampf(xi.z + dt * vi.z, S.lo[2], S.hi[2]);
-    v[s] = vi;
-    xs_pred[s] = make_float4(px, py, pz, 0.f);
-    lvl[s] = (uint8_t)L;
-    const float h = S.h;
-    int cx = cell_coord(px, S.lo[0], h, S.dims[0]);
-    int cy = cell_coord(py, S.lo[1], h, S.dims[1]);
-    int cz = cell_coord(pz, S.lo[2], h, S.dims[2]);
-    uint32_t k = S.cell_off + (uint32_t)(((int64_t)cz * S.dims[1] + cy) * S.dims[0] + cx);
-    key[s] = k;
-    ticket[s] = atomicAdd(&cell_count[k], 1u);
+    // Runs of lanes with equal keys (consecutive slots usually share a cell)
+    // take their tickets with one atomic issued by the run's first lane; all
+    // run heads of the wave issue together.
+    const uint32_t kprev = __shfl_up(k, 1, 64);
+    const bool head = valid && (lane == 0 || kprev != k);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = heads & ((2ull << lane) - 1ull);              // heads at or below lane
+    const int my_head = 63 - __clzll((long long)upto);                  // valid lanes have one
+    const uint64_t above = heads & ~((2ull << lane) - 1ull);
+    const uint64_t valid_mask = __ballot(valid);
+    const int run_end = above ? (__ffsll((unsigned long long)above) - 1)
+                              : (64 - __clzll((long long)valid_mask));  // one past the last valid lane
+    uint32_t base = 0;
+    if (head) base = atomicAdd(&cell_count[k], (uint32_t)(run_end - lane));
+    base = __shfl(base, valid ? my_head : lane, 64);
+    if (valid) ticket[s] = base + (uint32_t)(lane - my_head);
+    // sum of N_i over the block, for the running particle-iteration count
+    const uint32_t lsum = wave_sum((uint32_t)L);
+    if (lane == 0) wsum[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wsum[w];
+        level_part[blockIdx.x] = t;
+    }
 }
 
-// --------------------------------------------------- exclusive scan of cells
+// --------------------------------------------------- exclusive scans
 __global__ void k_scan_reduce(const uint32_t *__restrict__ in, uint32_t G,
                               uint32_t *__restrict__ part)
 {
@@ -252,109 +309,174 @@ __global__ void k_sort_finish(int64_t n, const uint32_t *__restrict__ tmp_src,
     key_out[f] = k;
 }
 
-// ------------------------------------------------------ neighbour lists
-// N_i = { j != i : |x*_i - x*_j|^2 < h^2 } over the 27 cells around x*_i:
-// nine x-contiguous slot ranges (rows dz, dy in {-1, 0, 1}), Fig. 7 second
-// loop.  Lists are written at the particle's level-bucket position t.
-__global__ void k_neighbours(int64_t n, const SceneDev *__restrict__ sc,
-                             const uint32_t *__restrict__ order, const float4 *__restrict__ xs,
-                             const float4 *__restrict__ x, const uint32_t *__restrict__ key,
-                             const uint32_t *__restrict__ cell_start, int cap,
-                             uint32_t *__restrict__ nbr, uint32_t *__restrict__ nmeta,
-                             uint32_t *__restrict__ err)
+
+// ------------------------------------------------------------------ tiles
+struct TileLoc {
+    const SceneDev *S;
+    int tx, ty, tz;
+};
+
+__device__ __forceinline__ TileLoc tile_locate(uint32_t tile, const uint32_t *__restrict__ tile_scene,
+                                               const SceneDev *__restrict__ sc)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const uint32_t i = order[t];
-    const int scn = __float_as_int(x[i].w);
-    const SceneDev &S = sc[scn];
-    const float h2 = S.h2;
-    const int gx = S.dims[0], gy = S.dims[1], gz = S.dims[2];
-    const uint32_t coff = S.cell_off;
-    const float4 xi = xs[i];
-    const uint32_t kl = key[i] - coff;
-    const int cx = (int)(kl % (uint32_t)gx);
-    const int cy = (int)((kl / (uint32_t)gx) % (uint32_t)gy);
-    const int cz = (int)(kl / ((uint32_t)gx * (uint32_t)gy));
-    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, gx - 1);
-    uint32_t cnt = 0;
-    for (int zz = max(cz - 1, 0); zz <= min(cz + 1, gz - 1); ++zz) {
-        for (int yy = max(cy - 1, 0); yy <= min(cy + 1, gy - 1); ++yy) {
-            const uint32_t row = coff + (uint32_t)(((int64_t)zz * gy + yy) * gx);
-            const uint32_t j0 = cell_start[row + x0], j1 = cell_start[row + x1 + 1];
-            for (uint32_t j = j0; j < j1; ++j) {
-                if (j == i) continue;
-                const float4 xj = xs[j];
-                const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < h2) {
-                    if (cnt < (uint32_t)cap) nbr[(size_t)cnt * n + t] = j;
-                    ++cnt;
-                }
-            }
+    TileLoc t;
+    t.S = &sc[tile_scene[tile]];
+    const uint32_t local = tile - t.S->tile_off;
+    const uint32_t nx = (uint32_t)t.S->tiles[0], ny = (uint32_t)t.S->tiles[1];
+    t.tx = (int)(local % nx);
+    t.ty = (int)((local / nx) % ny);
+    t.tz = (int)(local / (nx * ny));
+    return t;
+}
+
+// Slot where staged cell x (0..kStageEdge; kStageEdge = end) of staged row
+// (sy, sz) begins.  Staged cells run from one cell before the tile to one
+// after it; cells left or right of the grid are empty ranges, and rows above,
+// below, in front of or behind the grid are empty.
+__device__ __forceinline__ uint32_t row_bound(const TileLoc &t, const uint32_t *__restrict__ cell_start,
+                                              int sy, int sz, int x)
+{
+    const SceneDev &S = *t.S;
+    const int cy = t.ty * kTileEdge - 1 + sy, cz = t.tz * kTileEdge - 1 + sz;
+    if (cy < 0 || cy >= S.dims[1] || cz < 0 || cz >= S.dims[2]) return 0u;
+    const int cx = min(max(t.tx * kTileEdge - 1 + x, 0), S.dims[0]);
+    return cell_start[S.cell_off + ((uint32_t)cz * (uint32_t)S.dims[1] + (uint32_t)cy) *
+                                       (uint32_t)S.dims[0] + (uint32_t)cx];
+}
+
+// LDS tables of one tile: cell bounds of the 36 staged rows, LDS offset of
+// each row, and the prefix of own particles over the 16 own rows.
+struct TileTables {
+    uint32_t bnd[kStageRows][kStageEdge + 1];
+    uint32_t base[kStageRows + 1];
+    uint32_t own[kOwnRows + 1];
+};
+
+// fills tb (all threads call; ends with a barrier); returns whether the stage fits in LDS
+__device__ bool tile_tables(const TileLoc &t, const uint32_t *__restrict__ cell_start, TileTables &tb)
+{
+    for (int e = threadIdx.x; e < kStageRows * (kStageEdge + 1); e += blockDim.x) {
+        const int r = e / (kStageEdge + 1), x = e % (kStageEdge + 1);
+        tb.bnd[r][x] = row_bound(t, cell_start, r % kStageEdge, r / kStageEdge, x);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int r = 0; r < kStageRows; ++r) {
+            tb.base[r] = run;
+            run += tb.bnd[r][kStageEdge] - tb.bnd[r][0];
         }
+        tb.base[kStageRows] = run;
+        run = 0;
+        for (int o = 0; o < kOwnRows; ++o) {
+            const int r = (1 + o / kTileEdge) * kStageEdge + 1 + o % kTileEdge;
+            tb.own[o] = run;
+            run += tb.bnd[r][kTileEdge + 1] - tb.bnd[r][1];
+        }
+        tb.own[kOwnRows] = run;
     }
-    if (cnt > (uint32_t)cap) {
-        atomicOr(err, ERR_NEIGHBOUR_CAP);
-        cnt = (uint32_t)cap;
+    __syncthreads();
+    return tb.base[kStageRows] <= (uint32_t)kStageCap;
+}
+
+// copy the staged rows of `src` into LDS (all threads; ends with a barrier)
+__device__ __forceinline__ void tile_stage(const TileTables &tb, const float4 *__restrict__ src,
+                                           float4 *__restrict__ stage)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int r = wave; r < kStageRows; r += nw) {
+        const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0, b0 = tb.base[r];
+        for (uint32_t e = lane; e < len; e += 64) stage[b0 + e] = src[g0 + e];
     }
-    nmeta[t] = ((uint32_t)scn << 16) | cnt;
+    __syncthreads();
+}
+
+// Own particles and largest level of every tile: one wave per tile.
+__global__ void k_tile_prepare(uint32_t n_tiles, const SceneDev *__restrict__ sc,
+                               const uint32_t *__restrict__ tile_scene,
+                               const uint32_t *__restrict__ cell_start,
+                               const uint8_t *__restrict__ lvl, uint32_t *__restrict__ tile_count,
+                               uint8_t *__restrict__ tile_lvl)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;  // whole wave leaves together
+    const TileLoc t = tile_locate(tile, tile_scene, sc);
+    uint32_t a = 0, b = 0;
+    if (lane < kOwnRows) {
+        const int sy = 1 + lane % kTileEdge, sz = 1 + lane / kTileEdge;
+        a = row_bound(t, cell_start, sy, sz, 1);
+        b = row_bound(t, cell_start, sy, sz, kTileEdge + 1);
+    }
+    const uint32_t count = wave_sum(b - a);
+    uint32_t mx = 0;
+    for (int o = 0; o < kOwnRows; ++o) {
+        const uint32_t ao = __shfl(a, o, 64), bo = __shfl(b, o, 64);
+        for (uint32_t e = ao + lane; e < bo; e += 64) mx = max(mx, (uint32_t)lvl[e]);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) {
+        tile_count[tile] = count;
+        tile_lvl[tile] = (uint8_t)(count ? mx : 0u);
+    }
 }
 
 // ------------------------------------------------------- level buckets
-// Stable bucketing of slots by descending level (Eqs. 9-10: the active sets
-// are nested, so one bucketing per step makes every P_k a prefix).
-// counts layout: [(n_iters - L) * nb + block] for L = n_iters..1.
-__global__ void k_level_count(int64_t n, const uint8_t *__restrict__ lvl,
+// Stable bucketing of tiles by descending level 0..K (the active sets nest,
+// Eqs. 9-10, so one bucketing per step makes the tiles with active particles
+// of every iteration a prefix).  counts: [(K - L) * nb + block].
+__global__ void k_level_count(uint32_t m, const uint8_t *__restrict__ lvl,
                               uint32_t *__restrict__ counts, int nb, int K)
 {
     __shared__ uint32_t hist[PBF_MAX_ITERS + 1];
     for (int i = threadIdx.x; i <= K; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    int64_t s = (int64_t)blockIdx.x * kLevelBlock + threadIdx.x;
-    if (s < n) atomicAdd(&hist[lvl[s]], 1u);
+    const uint32_t s = blockIdx.x * kLevelBlock + threadIdx.x;
+    if (s < m) atomicAdd(&hist[lvl[s]], 1u);
     __syncthreads();
-    for (int L = threadIdx.x + 1; L <= K; L += blockDim.x)
+    for (int L = threadIdx.x; L <= K; L += blockDim.x)
         counts[(size_t)(K - L) * nb + blockIdx.x] = hist[L];
 }
 
-// single workgroup: exclusive scan of the bucket counts; count_ge[L] =
-// |{i : N_i >= L}| for L = 0..K+1 (count_ge[k + 1] = |P_k|).
+// single workgroup: exclusive scan of the bucket counts; ge[L] = number of
+// items with level >= L for L = 0..K+1; also counts the steps.
 __global__ void k_level_scan(uint32_t *__restrict__ counts, int nb, int K,
-                             uint32_t *__restrict__ count_ge,
-                             unsigned long long *__restrict__ totals)
+                             uint32_t *__restrict__ ge, const uint32_t *__restrict__ level_part,
+                             uint32_t n_part, unsigned long long *__restrict__ totals)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
-    const uint32_t M = (uint32_t)nb * (uint32_t)K;
+    const uint32_t M = (uint32_t)nb * (uint32_t)(K + 1);
     uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < M; b0 += blockDim.x) {
-        uint32_t i = b0 + threadIdx.x;
-        uint32_t v = i < M ? counts[i] : 0u;
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < M ? counts[i] : 0u;
         uint32_t tot;
-        uint32_t ex = block_exclusive_sum(v, lds, &tot);
+        const uint32_t ex = block_exclusive_sum(v, lds, &tot);
         if (i < M) counts[i] = carry + ex;
         carry += tot;
     }
+    // running count of particle-iterations (sum_i N_i) and of steps
+    uint32_t part = 0;
+    for (uint32_t e = threadIdx.x; e < n_part; e += blockDim.x) part += level_part[e];
+    part = wave_sum(part);
+    __shared__ uint32_t psum[1024 / 64];
+    if ((threadIdx.x & 63) == 0) psum[threadIdx.x >> 6] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
-        count_ge[0] = carry;
-        count_ge[1] = carry;
-        count_ge[K + 1] = 0;
-    }
-    for (int L = 2 + threadIdx.x; L <= K; L += blockDim.x)
-        count_ge[L] = counts[(size_t)(K - L + 1) * nb];
-    // running particle-iteration count: sum_L |{N_i >= L}| = sum_i N_i
-    if (threadIdx.x == 0) {
-        unsigned long long pit = carry;
-        for (int L = 2; L <= K; ++L) pit += counts[(size_t)(K - L + 1) * nb];
+        ge[0] = carry;
+        ge[K + 1] = 0;
+        unsigned long long pit = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) pit += psum[w];
         totals[0] += pit;
         totals[1] += 1ull;
     }
+    for (int L = 1 + threadIdx.x; L <= K; L += blockDim.x)
+        ge[L] = counts[(size_t)(K - L + 1) * nb];
 }
 
-// Rank of each slot among equal levels inside its wave by ballots, then
+// Rank of each item among equal levels inside its wave by ballots, then
 // across the block's waves, then the bucket offset of the block.
-__global__ void k_level_scatter(int64_t n, const uint8_t *__restrict__ lvl,
+__global__ void k_level_scatter(uint32_t m, const uint8_t *__restrict__ lvl,
                                 const uint32_t *__restrict__ offs, int nb, int K,
                                 uint32_t *__restrict__ order)
 {
@@ -363,111 +485,267 @@ __global__ void k_level_scatter(int64_t n, const uint8_t *__restrict__ lvl,
     for (int i = threadIdx.x; i < (kLevelBlock / 64) * (PBF_MAX_ITERS + 1); i += blockDim.x)
         (&wc[0][0])[i] = 0;
     __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * kLevelBlock + threadIdx.x;
-    const bool valid = s < n;
+    const uint32_t s = blockIdx.x * kLevelBlock + threadIdx.x;
+    const bool valid = s < m;
     const int L = valid ? (int)lvl[s] : 0;
     uint64_t rem = __ballot(valid);
     uint32_t rank = 0;
     while (rem) {
         const int leader = __ffsll((unsigned long long)rem) - 1;
         const int L0 = __shfl(L, leader, 64);
-        const uint64_t m = __ballot(valid && L == L0);
-        if (valid && L == L0) rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (lane == leader) wc[wave][L0] = (uint32_t)__popcll(m);
-        rem &= ~m;
+        const uint64_t mm = __ballot(valid && L == L0);
+        if (valid && L == L0) rank = (uint32_t)__popcll(mm & ((1ull << lane) - 1ull));
+        if (lane == leader) wc[wave][L0] = (uint32_t)__popcll(mm);
+        rem &= ~mm;
     }
     __syncthreads();
     if (valid) {
         uint32_t base = 0;
         for (int w = 0; w < wave; ++w) base += wc[w][L];
-        order[offs[(size_t)(K - L) * nb + blockIdx.x] + base + rank] = (uint32_t)s;
+        order[offs[(size_t)(K - L) * nb + blockIdx.x] + base + rank] = s;
+    }
+}
+
+// ------------------------------------------------------ neighbour lists
+// N_i = { j != i : |x*_i - x*_j|^2 < h^2 } over the 27 cells around x*_i
+// (Fig. 7 second loop), kept for every iteration of the step.  The 27 cells
+// are nine x-contiguous windows of three cells (rows dz, dy in {-1, 0, 1},
+// cells lx-1..lx+1) of the tile's LDS stage.  A neighbour is stored as a
+// 16-bit code: its index in the stage, or row << 10 | offset in the row when
+// the stage did not fit in LDS.  Codes are packed eight to a 16-byte group,
+// groups stored group-major (nbr[g * n + p]): one store per eight
+// neighbours here, fully coalesced loads in the solver passes.
+__global__ __launch_bounds__(kNbrThreads) void k_neighbours(
+    const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
+    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ cell_start,
+    const float4 *__restrict__ xs, const uint8_t *__restrict__ lvl, int64_t n, int cap,
+    uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta, uint32_t *__restrict__ pslot,
+    uint32_t *__restrict__ rows, uint32_t *__restrict__ err)
+{
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageCap];
+    if (blockIdx.x >= tile_ge[1]) return;  // empty tiles are not listed before this bound
+    const uint32_t tile = tile_order[blockIdx.x];
+    const TileLoc t = tile_locate(tile, tile_scene, sc);
+    const bool fits = tile_tables(t, cell_start, tb);
+    // keep the tables for the solver passes of this step
+    for (int e = threadIdx.x; e < kRowWords; e += blockDim.x)
+        rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
+    if (fits) tile_stage(tb, xs, stage);
+    const float h2 = t.S->h2;
+    const uint32_t p0 = tile_start[tile], nown = tb.own[kOwnRows];
+    uint32_t bad = 0;
+    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+        int o = 0;
+        while (tb.own[o + 1] <= pl) ++o;
+        const int sy = 1 + o % kTileEdge, sz = 1 + o / kTileEdge;
+        const int r = sz * kStageEdge + sy;
+        const uint32_t i = tb.bnd[r][1] + (pl - tb.own[o]);
+        int lx = 1;
+        while (lx < kTileEdge && tb.bnd[r][lx + 1] <= i) ++lx;  // x-cell of i, 1..kTileEdge
+        const float4 xi = fits ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
+        const size_t p = p0 + pl;
+        uint32_t cnt = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;  // eight pending codes
+#pragma unroll 1
+        for (int w = 0; w < 9; ++w) {
+            const int r2 = (sz + w / 3 - 1) * kStageEdge + (sy + w % 3 - 1);
+            const uint32_t g0 = tb.bnd[r2][0];
+            const uint32_t ja = tb.bnd[r2][lx - 1], len = tb.bnd[r2][lx + 2] - ja;
+            const uint32_t l0 = tb.base[r2] + (ja - g0);
+            for (uint32_t c0 = 0; c0 < len; c0 += 64) {
+                // distance test of up to 64 candidates into a bit mask ...
+                const uint32_t cl = min(len - c0, 64u);
+                uint64_t m = 0;
+                for (uint32_t c = 0; c < cl; ++c) {
+                    const float4 xj = fits ? stage[l0 + c0 + c] : xs[ja + c0 + c];
+                    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                    if (dx * dx + dy * dy + dz * dz < h2) m |= 1ull << c;
+                }
+                if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1ull << (i - ja - c0));  // not itself
+                // ... then its hits become codes, in candidate order
+                while (m) {
+                    const uint32_t c = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+                    m &= m - 1ull;
+                    uint32_t code;
+                    if (fits) {
+                        code = l0 + c;
+                    } else {
+                        const uint32_t off = ja + c - g0;
+                        if (off >= (1u << kSegOffBits)) bad |= ERR_CELL_CAP;
+                        code = ((uint32_t)r2 << kSegOffBits) | (off & ((1u << kSegOffBits) - 1));
+                    }
+                    const uint32_t v = code << ((cnt & 1u) * 16u);
+                    const uint32_t wd = (cnt >> 1) & 3u;
+                    b0 |= wd == 0 ? v : 0u;
+                    b1 |= wd == 1 ? v : 0u;
+                    b2 |= wd == 2 ? v : 0u;
+                    b3 |= wd == 3 ? v : 0u;
+                    ++cnt;
+                    if ((cnt & 7u) == 0) {
+                        if (cnt <= (uint32_t)cap)
+                            nbr[(size_t)((cnt >> 3) - 1) * n + p] = make_uint4(b0, b1, b2, b3);
+                        b0 = b1 = b2 = b3 = 0;
+                    }
+                }
+            }
+        }
+        if ((cnt & 7u) && cnt <= (uint32_t)cap) nbr[(size_t)(cnt >> 3) * n + p] = make_uint4(b0, b1, b2, b3);
+        if (cnt > (uint32_t)cap) {
+            bad |= ERR_NEIGHBOUR_CAP;
+            cnt = (uint32_t)cap & ~7u;  // only whole stored groups are valid
+        }
+        pslot[p] = i;
+        pmeta[p] = ((uint32_t)lvl[i] << kMetaLevel) | cnt;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// Tables of a tile saved by k_neighbours (cell bounds of the staged rows and
+// their LDS offsets): load them and stage `src` (all threads; ends with a
+// barrier); returns whether the stage fits in LDS.
+__device__ __forceinline__ bool stage_rows(const uint32_t *__restrict__ rows, uint32_t tile,
+                                           const float4 *__restrict__ src, TileTables &tb,
+                                           float4 *__restrict__ stage)
+{
+    for (int e = threadIdx.x; e < kRowWords; e += blockDim.x) {
+        const uint32_t w = rows[(size_t)tile * kRowWords + e];
+        if (e < kBndWords) (&tb.bnd[0][0])[e] = w;
+        else tb.base[e - kBndWords] = w;
+    }
+    __syncthreads();
+    const bool fits = tb.base[kStageRows] <= (uint32_t)kStageCap;
+    if (fits) tile_stage(tb, src, stage);
+    return fits;
+}
+
+// Walk the neighbour list of particle p in stored order, calling f(position
+// and lambda of the neighbour); codes are read eight at a time.
+template <class F>
+__device__ __forceinline__ void for_each_neighbour(const TileTables &tb, bool fits,
+                                                   const float4 *__restrict__ stage,
+                                                   const float4 *__restrict__ src,
+                                                   const uint4 *__restrict__ nbr, int64_t n,
+                                                   size_t p, uint32_t cnt, F &&f)
+{
+    auto get = [&](uint32_t c) -> float4 {
+        return fits ? stage[c] : src[tb.bnd[c >> kSegOffBits][0] + (c & ((1u << kSegOffBits) - 1))];
+    };
+    for (uint32_t q = 0; q < cnt; q += 8) {
+        const uint4 v = nbr[(size_t)(q >> 3) * n + p];
+        const uint32_t cc[8] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16,
+                                v.z & 0xffffu, v.z >> 16, v.w & 0xffffu, v.w >> 16};
+        const uint32_t m = min(cnt - q, 8u);
+        float4 xj[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xj[u] = (uint32_t)u < m ? get(cc[u]) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if ((uint32_t)u < m) f(xj[u]);
     }
 }
 
 // ------------------------------------------------ solver iteration k
-// lambda_i for i in P_k (Eqs. 4-6), written to xs[i].w.  Neighbours read
-// only xyz of the same buffer, so the 4-byte write of w does not disturb them.
-__global__ void k_lambda(int k, int64_t n, const SceneDev *__restrict__ sc,
-                         const uint32_t *__restrict__ count_ge,
-                         const uint32_t *__restrict__ order, float4 *__restrict__ xs,
-                         const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nmeta)
+// lambda_i for the active particles of the tile (Eqs. 4-6), written to
+// xs[i].w; neighbours read only xyz of the same buffer.
+__global__ __launch_bounds__(kTileThreads) void k_lambda(
+    int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
+    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
+    const uint32_t *__restrict__ rows, float4 *__restrict__ xs, int64_t n,
+    const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
+    const uint32_t *__restrict__ pslot)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)count_ge[k + 1]) return;
-    const uint32_t i = order[t];
-    const uint32_t meta = nmeta[t];
-    const int cnt = (int)(meta & 0xffffu);
-    const SceneDev &S = sc[meta >> 16];
-    const float h = S.h, h2 = S.h2, cg = S.c_grad;
-    const float4 xi = xs[i];
-    float sum6 = S.h6;  // the particle itself: (h^2 - 0)^3
-    float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
-    for (int q = 0; q < cnt; ++q) {
-        const uint32_t j = nbr[(size_t)q * n + t];
-        const float4 xj = xs[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < h2) {
-            const float w = h2 - r2;
-            sum6 += w * w * w;
-            if (r2 > 0.f) {
-                const float ir = rsqrtf(r2);
-                const float hr = h - r2 * ir;
-                const float f = -cg * hr * hr * ir;  // grad W = f d
-                gx += f * dx;
-                gy += f * dy;
-                gz += f * dz;
-                g2 += f * f * r2;
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageCap];
+    if (blockIdx.x >= tile_ge[k + 1]) return;
+    const uint32_t tile = tile_order[blockIdx.x];
+    const SceneDev &S = sc[tile_scene[tile]];
+    const bool fits = stage_rows(rows, tile, xs, tb, stage);
+    const float h = S.h, h2 = S.h2, cg = S.c_grad, h6 = S.h6, crho = S.c_rho, cs = S.c_s,
+                eps = S.eps;
+    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+        const size_t p = p0 + pl;
+        const uint32_t meta = pmeta[p];
+        if ((int)(meta >> kMetaLevel) <= k) continue;
+        const uint32_t i = pslot[p];
+        const float4 xi = xs[i];
+        float sum6 = h6;  // the particle itself: (h^2 - 0)^3
+        float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
+        for_each_neighbour(tb, fits, stage, xs, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < h2) {
+                const float w = h2 - r2;
+                sum6 += w * w * w;
+                if (r2 > 0.f) {
+                    const float ir = rsqrtf(r2);
+                    const float hr = h - r2 * ir;
+                    const float f = -cg * hr * hr * ir;  // grad W = f d
+                    gx += f * dx;
+                    gy += f * dy;
+                    gz += f * dz;
+                    g2 += f * f * r2;
+                }
             }
-        }
+        });
+        const float C = crho * sum6 - 1.f;
+        const float denom = cs * (gx * gx + gy * gy + gz * gz + g2) + eps;
+        xs[i].w = -C / denom;
     }
-    const float C = S.c_rho * sum6 - 1.f;
-    const float denom = S.c_s * (gx * gx + gy * gy + gz * gz + g2) + S.eps;
-    xs[i].w = -C / denom;
 }
 
-// Delta p_i for i in P_k (Eq. 7) with the wall contact (clamp), written to
-// the other buffer (Jacobi).  Particles that finished with this iteration
-// (N_i == k) copy position and lambda across, so that from now on both
-// buffers hold their final values and they need no further work.
-__global__ void k_update(int k, int64_t n, const SceneDev *__restrict__ sc,
-                         const uint32_t *__restrict__ count_ge,
-                         const uint32_t *__restrict__ order, const float4 *__restrict__ xs_in,
-                         float4 *__restrict__ xs_out, const uint32_t *__restrict__ nbr,
-                         const uint32_t *__restrict__ nmeta)
+// Delta p_i for the active particles of the tile (Eq. 7) with the wall
+// contact (clamp), written to the other buffer (Jacobi).  Particles that
+// finished with this iteration (N_i == k) copy position and lambda across,
+// so that both buffers hold their final values from now on.
+__global__ __launch_bounds__(kTileThreads) void k_update(
+    int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
+    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
+    const uint32_t *__restrict__ rows, const float4 *__restrict__ xs_in,
+    float4 *__restrict__ xs_out, int64_t n, const uint4 *__restrict__ nbr,
+    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)count_ge[k]) return;
-    const uint32_t i = order[t];
-    const float4 xi = xs_in[i];
-    if (t >= (int64_t)count_ge[k + 1]) {
-        xs_out[i] = xi;
-        return;
-    }
-    const uint32_t meta = nmeta[t];
-    const int cnt = (int)(meta & 0xffffu);
-    const SceneDev &S = sc[meta >> 16];
-    const float h = S.h, h2 = S.h2, cg = S.c_grad;
-    const float li = xi.w;
-    float px = 0.f, py = 0.f, pz = 0.f;
-    for (int q = 0; q < cnt; ++q) {
-        const uint32_t j = nbr[(size_t)q * n + t];
-        const float4 xj = xs_in[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < h2 && r2 > 0.f) {
-            const float ir = rsqrtf(r2);
-            const float hr = h - r2 * ir;
-            const float f = -cg * hr * hr * ir * (li + xj.w);
-            px += f * dx;
-            py += f * dy;
-            pz += f * dz;
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageCap];
+    if (blockIdx.x >= tile_ge[k > 1 ? k : 1]) return;  // tiles with a particle of level >= k
+    const uint32_t tile = tile_order[blockIdx.x];
+    const SceneDev &S = sc[tile_scene[tile]];
+    const bool fits = stage_rows(rows, tile, xs_in, tb, stage);
+    const float h = S.h, h2 = S.h2, cg = S.c_grad, sr = S.inv_rho0;
+    const float lo0 = S.lo[0], lo1 = S.lo[1], lo2 = S.lo[2];
+    const float hi0 = S.hi[0], hi1 = S.hi[1], hi2 = S.hi[2];
+    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+        const size_t p = p0 + pl;
+        const uint32_t meta = pmeta[p];
+        const int L = (int)(meta >> kMetaLevel);
+        if (L < k) continue;
+        const uint32_t i = pslot[p];
+        const float4 xi = xs_in[i];
+        if (L == k) {
+            xs_out[i] = xi;
+            continue;
         }
+        const float li = xi.w;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        for_each_neighbour(tb, fits, stage, xs_in, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < h2 && r2 > 0.f) {
+                const float ir = rsqrtf(r2);
+                const float hr = h - r2 * ir;
+                const float f = -cg * hr * hr * ir * (li + xj.w);
+                px += f * dx;
+                py += f * dy;
+                pz += f * dz;
+            }
+        });
+        xs_out[i] = make_float4(clampf(xi.x + px * sr, lo0, hi0), clampf(xi.y + py * sr, lo1, hi1),
+                                clampf(xi.z + pz * sr, lo2, hi2), li);
     }
-    const float s = S.inv_rho0;
-    xs_out[i] = make_float4(clampf(xi.x + px * s, S.lo[0], S.hi[0]),
-                            clampf(xi.y + py * s, S.lo[1], S.hi[1]),
-                            clampf(xi.z + pz * s, S.lo[2], S.hi[2]), li);
 }
 
 // --------------------------------------------- velocity and position update
@@ -485,71 +763,7 @@ __global__ void k_commit(int64_t n, const SceneDev *__restrict__ sc, float4 *__r
     x[s] = make_float4(p.x, p.y, p.z, xi.w);
 }
 
-inline unsigned blocks_for(int64_t n, int block)
-{
-    return (unsigned)((n + block - 1) / block);
-}
 
-}  // namespace
-
-#define LAUNCH(KID, GRID, BLOCK, KERNEL, ...)                              \
-    do {                                                                   \
-        if (tm) timer_begin(tm, KID, s);                                   \
-        hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        if (tm) timer_end(tm, KID, s);                                     \
-        hipError_t e_ = hipGetLastError();                                 \
-        if (e_ != hipSuccess) return e_;                                   \
-    } while (0)
-
-hipError_t enqueue_step(const StepBuffers &b, int cur, const LaunchShape &ls, hipStream_t s,
-                        Timer *tm)
-{
-    const int64_t n = b.n;
-    if (n == 0) return hipSuccess;
-    const int nxt = cur ^ 1;
-    const int K = b.n_iters;
-    const uint32_t G = b.n_cells;
-    const int *bs = ls.block;
-
-    LAUNCH(K_FILL, blocks_for(G, bs[K_FILL]), bs[K_FILL], k_fill, b.cell_count, G, 0u);
-    LAUNCH(K_LOD_PREDICT, blocks_for(n, bs[K_LOD_PREDICT]), bs[K_LOD_PREDICT], k_lod_predict, n,
-           b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.xs_pred, b.lvl[cur],
-           b.key_pre, b.ticket, b.cell_count);
-    LAUNCH(K_SCAN_REDUCE, b.n_scan_blocks, kScanBlock, k_scan_reduce, b.cell_count, G,
-           b.scan_part);
-    LAUNCH(K_SCAN_TOP, 1, 1024, k_scan_top, b.scan_part, (uint32_t)b.n_scan_blocks);
-    LAUNCH(K_SCAN_APPLY, b.n_scan_blocks, kScanBlock, k_scan_apply, b.cell_count, G, b.scan_part,
-           b.cell_start);
-    LAUNCH(K_SORT_SCATTER, blocks_for(n, bs[K_SORT_SCATTER]), bs[K_SORT_SCATTER], k_sort_scatter,
-           n, b.key_pre, b.ticket, b.cell_start, b.id[cur], b.tmp_src, b.tmp_id);
-    LAUNCH(K_SORT_FINISH, blocks_for(n, bs[K_SORT_FINISH]), bs[K_SORT_FINISH], k_sort_finish, n,
-           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.v[cur], b.xs_pred,
-           b.lvl[cur], b.x[nxt], b.v[nxt], b.xs[0], b.id[nxt], b.lvl[nxt], b.key, b.err);
-    LAUNCH(K_LEVEL_COUNT, b.n_level_blocks, kLevelBlock, k_level_count, n, b.lvl[nxt],
-           b.level_counts, b.n_level_blocks, K);
-    LAUNCH(K_LEVEL_SCAN, 1, 1024, k_level_scan, b.level_counts, b.n_level_blocks, K, b.count_ge,
-           b.totals);
-    LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, n, b.lvl[nxt],
-           b.level_counts, b.n_level_blocks, K, b.order);
-    LAUNCH(K_NEIGHBOURS, blocks_for(n, bs[K_NEIGHBOURS]), bs[K_NEIGHBOURS], k_neighbours, n,
-           b.scenes, b.order, b.xs[0], b.x[nxt], b.key, b.cell_start, b.nbr_cap, b.nbr, b.nmeta,
-           b.err);
-    for (int k = 0; k < K; ++k) {
-        float4 *xin = b.xs[k & 1], *xout = b.xs[(k + 1) & 1];
-        LAUNCH(K_LAMBDA, blocks_for(n, bs[K_LAMBDA]), bs[K_LAMBDA], k_lambda, k, n, b.scenes,
-               b.count_ge, b.order, xin, b.nbr, b.nmeta);
-        LAUNCH(K_UPDATE, blocks_for(n, bs[K_UPDATE]), bs[K_UPDATE], k_update, k, n, b.scenes,
-               b.count_ge, b.order, xin, xout, b.nbr, b.nmeta);
-    }
-    LAUNCH(K_COMMIT, blocks_for(n, bs[K_COMMIT]), bs[K_COMMIT], k_commit, n, b.scenes, b.x[nxt],
-           b.v[nxt], b.xs[K & 1], b.err);
-    return hipSuccess;
-}
-
-}  // namespace pbf
-
-namespace pbf {
-namespace {
 // out[3 (id - id_lo) + c] = x[s].c for particles with id in [id_lo, id_hi)
 __global__ void k_unpermute(int64_t n, const float4 *__restrict__ x,
                             const uint32_t *__restrict__ id, float *__restrict__ out,
@@ -565,7 +779,103 @@ __global__ void k_unpermute(int64_t n, const float4 *__restrict__ x,
     out[o + 1] = p.y;
     out[o + 2] = p.z;
 }
+
+inline unsigned blocks_for(int64_t n, int block)
+{
+    return (unsigned)((n + block - 1) / block);
+}
+
 }  // namespace
+
+#define LAUNCH(KID, GRID, BLOCK, KERNEL, ...)                                   \
+    do {                                                                        \
+        if (tm) timer_begin(tm, KID, s);                                        \
+        hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        if (tm) timer_end(tm, KID, s);                                          \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) return e_;                                        \
+    } while (0)
+
+static hipError_t enqueue_scan(const uint32_t *in, uint32_t count, uint32_t *part, uint32_t *out,
+                               hipStream_t s, Timer *tm)
+{
+    const unsigned nb = blocks_for(count, kScanBlock * kScanItems);
+    LAUNCH(K_SCAN_REDUCE, nb, kScanBlock, k_scan_reduce, in, count, part);
+    LAUNCH(K_SCAN_TOP, 1, 1024, k_scan_top, part, nb);
+    LAUNCH(K_SCAN_APPLY, nb, kScanBlock, k_scan_apply, in, count, part, out);
+    return hipSuccess;
+}
+
+hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, hipStream_t s,
+                        Timer *tm, const StepRecord *rec)
+{
+    StepBuffers b = b0;
+    if (rec) {  // a recorded step keeps its neighbour structure in the record
+        b.nbr = rec->nbr;
+        b.pmeta = rec->pmeta;
+        b.pslot = rec->pslot;
+        b.tile_rows = rec->tile_rows;
+        b.tile_order = rec->tile_order;
+        b.tile_start = rec->tile_start;
+        b.tile_count = rec->tile_count;
+        b.tile_ge = rec->tile_ge;
+    }
+    const int64_t n = b.n;
+    if (n == 0) return hipSuccess;
+    const int nxt = cur ^ 1;
+    const int K = b.n_iters;
+    const uint32_t G = b.n_cells, T = b.n_tiles;
+    const int *bs = ls.block;
+    hipError_t e;
+
+    LAUNCH(K_FILL, blocks_for(G, bs[K_FILL]), bs[K_FILL], k_fill, b.cell_count, G, 0u);
+    LAUNCH(K_LOD_PREDICT, blocks_for(n, bs[K_LOD_PREDICT]), bs[K_LOD_PREDICT], k_lod_predict, n,
+           b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.xs_pred, b.lvl[cur],
+           b.key_pre, b.ticket, b.cell_count, b.level_part);
+    if ((e = enqueue_scan(b.cell_count, G, b.scan_part, b.cell_start, s, tm)) != hipSuccess) return e;
+    LAUNCH(K_SORT_SCATTER, blocks_for(n, bs[K_SORT_SCATTER]), bs[K_SORT_SCATTER], k_sort_scatter,
+           n, b.key_pre, b.ticket, b.cell_start, b.id[cur], b.tmp_src, b.tmp_id);
+    LAUNCH(K_SORT_FINISH, blocks_for(n, bs[K_SORT_FINISH]), bs[K_SORT_FINISH], k_sort_finish, n,
+           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.v[cur], b.xs_pred,
+           b.lvl[cur], b.x[nxt], b.v[nxt], b.xs[0], b.id[nxt], b.lvl[nxt], b.key, b.err);
+    // tiles: own counts and levels, their prefix, and the level buckets
+    LAUNCH(K_TILE_PREPARE, blocks_for((int64_t)T * 64, bs[K_TILE_PREPARE]), bs[K_TILE_PREPARE],
+           k_tile_prepare, T, b.scenes, b.tile_scene, b.cell_start, b.lvl[nxt], b.tile_count,
+           b.tile_lvl);
+    if ((e = enqueue_scan(b.tile_count, T, b.scan_part, b.tile_start, s, tm)) != hipSuccess) return e;
+    LAUNCH(K_LEVEL_COUNT, b.n_level_blocks, kLevelBlock, k_level_count, T, b.tile_lvl,
+           b.level_counts, b.n_level_blocks, K);
+    LAUNCH(K_LEVEL_SCAN, 1, 1024, k_level_scan, b.level_counts, b.n_level_blocks, K, b.tile_ge,
+           b.level_part, blocks_for(n, bs[K_LOD_PREDICT]), b.totals);
+    LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
+           b.level_counts, b.n_level_blocks, K, b.tile_order);
+    LAUNCH(K_NEIGHBOURS, T, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
+           b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap, b.nbr,
+           b.pmeta, b.pslot, b.tile_rows, b.err);
+    for (int k = 0; k < K; ++k) {
+        float4 *xin = b.xs[k & 1], *xout = b.xs[(k + 1) & 1];
+        LAUNCH(K_LAMBDA, T, bs[K_LAMBDA], k_lambda, k, b.scenes, b.tile_scene, b.tile_order,
+               b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr, b.pmeta,
+               b.pslot);
+        if (rec && (e = hipMemcpyAsync(rec->snap[k], xin, sizeof(float4) * n,
+                                       hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return e;
+        LAUNCH(K_UPDATE, T, bs[K_UPDATE], k_update, k, b.scenes, b.tile_scene, b.tile_order,
+               b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, xout, n, b.nbr, b.pmeta,
+               b.pslot);
+    }
+    if (rec) {
+        if ((e = hipMemcpyAsync(rec->snap[K], b.xs[K & 1], sizeof(float4) * n,
+                                hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(rec->id, b.id[nxt], sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
+                                s)) != hipSuccess ||
+            (e = hipMemcpyAsync(rec->lvl, b.lvl[nxt], n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return e;
+    }
+    LAUNCH(K_COMMIT, blocks_for(n, bs[K_COMMIT]), bs[K_COMMIT], k_commit, n, b.scenes, b.x[nxt],
+           b.v[nxt], b.xs[K & 1], b.err);
+    return hipSuccess;
+}
 
 hipError_t enqueue_unpermute(int64_t n, const float4 *x, const uint32_t *id, float *out,
                              uint32_t id_lo, uint32_t id_hi, hipStream_t s)
@@ -575,4 +885,5 @@ hipError_t enqueue_unpermute(int64_t n, const float4 *x, const uint32_t *id, flo
                        id_lo, id_hi);
     return hipGetLastError();
 }
+
 }  // namespace pbf

@@ -267,3 +267,35 @@ def test_full_size_one_step(name):
         sim.sync()
         err = _check_step(sc, sim, x_ref, v_ref, info, nbr_sample=sample)
         print(f"{name}: max position error {err:.3e} (tolerance {pos_tol(sc):.1e})")
+
+
+def _rod_scene():
+    """A lattice block with 80 extra particles squeezed into three cells of one
+    grid row: that candidate window holds more than 64 particles while the
+    tile's stage still fits in LDS."""
+    base = scenes.block(8, 8, 8, seed=31, n_min=2, n_max=4, levels="random", vel_sigma=0.1)
+    rng = np.random.default_rng(32)
+    rod = rng.uniform((0.301, 0.201, 0.201), (0.599, 0.299, 0.299), size=(80, 3))
+    x = np.concatenate([base.x0.astype(np.float64), rod])
+    v = np.concatenate([base.v0.astype(np.float64), np.zeros_like(rod)])
+    lv = np.concatenate([base.levels, rng.integers(2, 5, size=80)]).astype(np.uint8)
+    sc = scenes.Scene(name="rod", x0=x, v0=v, lo=base.lo, hi=base.hi, n_min=2, n_max=4)
+    return sc.with_lod(scenes.LOD_EXPLICIT, levels=lv)
+
+
+@pytest.mark.parametrize("case", ["dense_window", "stage_overflow"])
+def test_dense_inputs(case):
+    """Candidate windows beyond 64 particles (second mask word) and tiles whose
+    stage does not fit in LDS (neighbours read from HBM)."""
+    if case == "dense_window":
+        sc = _rod_scene()
+    else:
+        sc = scenes.random_cloud(16000, seed=41, extent=1.0, n_min=1, n_max=3, dup_frac=0.0)
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    counts = info["nbr_count"]
+    sens_x, sens_l = ulp_sensitivity(sc)
+    tol = max(pos_tol(sc), 4.0 * sens_x)
+    print(f"{case}: n={sc.n}, max neighbours {counts.max()}, tolerance {tol:.2e}")
+    with _sim(sc, max_neighbours=1000) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info, tol=tol, lam_extra=4.0 * sens_l)
