@@ -80,6 +80,11 @@ def lib():
         L.orc_density.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
         L.orc_apbf_step_fixed.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_apbf_step_fixed_vjp.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_spiky_hess.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_double)]
         L.orc_levels.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod), ctypes.c_void_p,
                                  ctypes.c_void_p]
         L.orc_cell_keys.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
@@ -271,6 +276,49 @@ def apbf_step_fixed(scene, x, v, levels, nbr_off, nbr_ids):
     if rc != ORC_OK:
         raise ValueError(f"orc_apbf_step_fixed failed ({rc})")
     return x, v
+
+
+def spiky_hess(d, h: float) -> np.ndarray:
+    """3x3 Jacobian of spiky_grad with respect to p_i at d = p_i - p_j."""
+    d = np.ascontiguousarray(d, np.float64)
+    out = np.zeros(9, np.float64)
+    lib().orc_spiky_hess(_ptr(d, ctypes.c_double), float(h), _ptr(out, ctypes.c_double))
+    return out.reshape(3, 3)
+
+
+def apbf_step_fixed_vjp(scene, x, v, levels, nbr_off, nbr_ids, gx, gv):
+    """Reverse mode of apbf_step_fixed at (x, v): the adjoints (gx, gv) of
+    the step's outputs (x', v') in, those of (x, v) out (float64, by ID)."""
+    p = params(scene)
+    x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1, 3))
+    v = np.ascontiguousarray(np.asarray(v, np.float64).reshape(-1, 3))
+    gx = np.array(gx, np.float64, order="C").reshape(-1, 3)
+    gv = np.array(gv, np.float64, order="C").reshape(-1, 3)
+    lv = np.ascontiguousarray(levels, np.int32)
+    off = np.ascontiguousarray(nbr_off, np.int64)
+    ids = np.ascontiguousarray(nbr_ids, np.int32)
+    if ids.size == 0:
+        ids = np.zeros(1, np.int32)
+    rc = lib().orc_apbf_step_fixed_vjp(ctypes.byref(p), lv.ctypes.data, off.ctypes.data,
+                                       ids.ctypes.data, x.ctypes.data, v.ctypes.data,
+                                       gx.ctypes.data, gv.ctypes.data)
+    if rc != ORC_OK:
+        raise ValueError(f"orc_apbf_step_fixed_vjp failed ({rc})")
+    return gx, gv
+
+
+def rollout_vjp(scene, x, v, frozen, gx, gv):
+    """Reverse mode of rollout_fixed from (x, v): replays the steps keeping
+    every step's input state, then applies the step adjoints last to first."""
+    states = []
+    x = np.asarray(x, np.float64)
+    v = np.asarray(v, np.float64)
+    for lv, off, ids in frozen:
+        states.append((x, v))
+        x, v = apbf_step_fixed(scene, x, v, lv, off, ids)
+    for (xs, vs), (lv, off, ids) in zip(reversed(states), reversed(frozen)):
+        gx, gv = apbf_step_fixed_vjp(scene, xs, vs, lv, off, ids, gx, gv)
+    return gx, gv
 
 
 def rollout_structure(scene, x, v, steps):

@@ -229,7 +229,7 @@ static int find_neighbours(const orc_params *p, const double *xs, const int32_t 
  * to p_i is (m/rho0) sum_j grad W_ij and with respect to p_j it is
  * -(m/rho0) grad W_ij; each is weighted by w = 1/m. */
 static double lambda_of(const orc_params *p, const double *xs, int32_t i,
-                        const int32_t *nb, int64_t cnt, double *rho_out)
+                        const int32_t *nb, int64_t cnt, double *rho_out, double *s_out)
 {
     const double *xi = xs + 3 * (int64_t)i;
     const double w = 1.0 / p->mass;
@@ -252,6 +252,7 @@ static double lambda_of(const orc_params *p, const double *xs, int32_t i,
     double C = rho / p->rho0 - 1.0;
     double denom = w * (gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2]) + sum_wj;
     if (rho_out) *rho_out = rho;
+    if (s_out) *s_out = denom;
     return -C / (denom + p->eps);
 }
 
@@ -409,7 +410,7 @@ int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v,
     for (int32_t k = 0; k < K; ++k) {
 #pragma omp parallel for schedule(dynamic, 256)
         for (int32_t i = 0; i < n; ++i)
-            if (lev[i] > k) lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL);
+            if (lev[i] > k) lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL, NULL);
 #pragma omp parallel for schedule(dynamic, 256)
         for (int32_t i = 0; i < n; ++i)
             if (lev[i] > k) delta_p_of(p, xs, lam, i, ids + off[i], off[i + 1] - off[i], dp + 3 * (int64_t)i);
@@ -465,7 +466,7 @@ int orc_apbf_step_fixed(const orc_params *p, const int32_t *lev, const int64_t *
     for (int32_t k = 0; k < K; ++k) {
 #pragma omp parallel for schedule(dynamic, 256)
         for (int32_t i = 0; i < n; ++i)
-            if (lev[i] > k) lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL);
+            if (lev[i] > k) lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL, NULL);
 #pragma omp parallel for schedule(dynamic, 256)
         for (int32_t i = 0; i < n; ++i)
             if (lev[i] > k) delta_p_of(p, xs, lam, i, ids + off[i], off[i + 1] - off[i], dp + 3 * (int64_t)i);
@@ -482,6 +483,199 @@ int orc_apbf_step_fixed(const orc_params *p, const int32_t *lev, const int64_t *
     }
 done:
     free(xs); free(dp); free(lam);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* reverse mode of the fixed-structure step                            */
+/* ------------------------------------------------------------------ */
+
+/* Hessian of the spiky kernel with respect to p_i at d = p_i - p_j, i.e. the
+ * Jacobian of orc_spiky_grad: with grad W = phi(r) d and
+ * phi(r) = -45/(pi h^6) (h - r)^2 / r, it is phi I + (phi'(r) / r) d d^T,
+ * phi'(r) = 45/(pi h^6) (h - r)(h + r) / r^2.  Zero outside 0 < r < h. */
+void orc_spiky_hess(const double d[3], double h, double H[9])
+{
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int e = 0; e < 9; ++e) H[e] = 0.0;
+    if (r <= 0.0 || r >= h) return;
+    double k = 45.0 / (M_PI * pow(h, 6));
+    double phi = -k * (h - r) * (h - r) / r;
+    double dphi_r = k * (h - r) * (h + r) / (r * r * r);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) H[3 * a + b] = (a == b ? phi : 0.0) + dphi_r * d[a] * d[b];
+}
+
+/* Gradient of the poly6 kernel with respect to p_i at d = p_i - p_j:
+ * -6 * 315/(64 pi h^9) (h^2 - r^2)^2 d for r < h. */
+static void poly6_grad(const double d[3], double h, double out[3])
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    out[0] = out[1] = out[2] = 0.0;
+    if (r2 >= h * h) return;
+    double t = h * h - r2;
+    double c = -6.0 * 315.0 / (64.0 * M_PI * pow(h, 9)) * t * t;
+    out[0] = c * d[0];
+    out[1] = c * d[1];
+    out[2] = c * d[2];
+}
+
+static void mat_vec_add(const double H[9], const double u[3], double s, double *acc)
+{
+    for (int a = 0; a < 3; ++a) acc[a] += s * (H[3 * a] * u[0] + H[3 * a + 1] * u[1] + H[3 * a + 2] * u[2]);
+}
+
+/* Vector-Jacobian product of orc_apbf_step_fixed: given (x, v) at the start
+ * of the step and the adjoints gx, gv of the step's outputs (x', v'), both
+ * float[3n] by particle ID, overwrite gx, gv with the adjoints of (x, v).
+ * Levels, neighbour sets and the wall contacts of the forward step are held
+ * fixed (the chain rule through Eqs. 4-7 with the gating of Eqs. 9-11 and the
+ * prediction and update of Fig. 7).  Each pair's contribution is scattered
+ * to both of its particles, following the forward formulas term by term:
+ * the forward pass is recomputed and kept per iteration, then the iterations
+ * are reversed. */
+int orc_apbf_step_fixed_vjp(const orc_params *p, const int32_t *lev, const int64_t *off,
+                            const int32_t *ids, const double *x, const double *v, double *gx,
+                            double *gv)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int32_t n = p->n;
+    const int32_t K = p->n_max;
+    const size_t n3 = (size_t)n * 3, nn = (size_t)(n ? n : 1);
+    const double m = p->mass, rho0 = p->rho0, dt = p->dt;
+    double *z = (double *)malloc(sizeof(double) * (K + 1) * (n3 ? n3 : 1));  /* z^k, k = 0..K */
+    double *u = (double *)malloc(sizeof(double) * (K + 1) * (n3 ? n3 : 1));  /* pre-clamp values */
+    double *lam = (double *)calloc((size_t)(K ? K : 1) * nn, sizeof(double)); /* lambda used at k */
+    double *Cv = (double *)calloc((size_t)(K ? K : 1) * nn, sizeof(double));
+    double *Sv = (double *)calloc((size_t)(K ? K : 1) * nn, sizeof(double));
+    double *bz = (double *)calloc(n3 ? n3 : 1, sizeof(double));
+    double *bdp = (double *)calloc(n3 ? n3 : 1, sizeof(double));
+    double *bl = (double *)calloc(nn, sizeof(double));
+    if (!z || !u || !lam || !Cv || !Sv || !bz || !bdp || !bl) { rc = ORC_ERR_MEM; goto done; }
+    for (int32_t i = 0; i < n; ++i) {
+        if (lev[i] < p->n_min || lev[i] > p->n_max) { rc = ORC_ERR_ARG; goto done; }
+        for (int d = 0; d < 3; ++d) {
+            double v1 = v[3 * (int64_t)i + d] + dt * p->g[d];
+            u[3 * (int64_t)i + d] = x[3 * (int64_t)i + d] + dt * v1;
+            z[3 * (int64_t)i + d] = u[3 * (int64_t)i + d];
+        }
+        clamp_box(p, z + 3 * (int64_t)i);
+    }
+    /* forward, keeping z^k, the unclamped values, lambda, C and S per iteration */
+    for (int32_t k = 0; k < K; ++k) {
+        const double *zk = z + (size_t)k * n3;
+        double *zn = z + (size_t)(k + 1) * n3, *un = u + (size_t)(k + 1) * n3;
+        double *lk = lam + (size_t)k * nn;
+        if (k > 0) memcpy(lk, lam + (size_t)(k - 1) * nn, sizeof(double) * n);
+        for (int32_t i = 0; i < n; ++i) {
+            if (lev[i] <= k) continue;
+            double rho;
+            lk[i] = lambda_of(p, zk, i, ids + off[i], off[i + 1] - off[i], &rho,
+                              Sv + (size_t)k * nn + i);
+            Cv[(size_t)k * nn + i] = rho / rho0 - 1.0;
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) zn[3 * (int64_t)i + d] = zk[3 * (int64_t)i + d];
+            if (lev[i] <= k) continue;
+            double dp[3];
+            delta_p_of(p, zk, lk, i, ids + off[i], off[i + 1] - off[i], dp);
+            for (int d = 0; d < 3; ++d) un[3 * (int64_t)i + d] = zk[3 * (int64_t)i + d] + dp[d];
+            for (int d = 0; d < 3; ++d) zn[3 * (int64_t)i + d] = un[3 * (int64_t)i + d];
+            clamp_box(p, zn + 3 * (int64_t)i);
+        }
+    }
+    /* x' = z^K, v' = (z^K - x) / dt */
+    for (size_t e = 0; e < n3; ++e) {
+        bz[e] = gx[e] + gv[e] / dt;
+        gx[e] = -gv[e] / dt;
+    }
+    for (int32_t k = K - 1; k >= 0; --k) {
+        const double *zk = z + (size_t)k * n3, *un = u + (size_t)(k + 1) * n3;
+        const double *lk = lam + (size_t)k * nn;
+        /* clamp of the active particles' update */
+        for (int32_t i = 0; i < n; ++i)
+            for (int d = 0; d < 3; ++d) {
+                size_t e = 3 * (size_t)i + d;
+                if (lev[i] <= k) { bdp[e] = 0.0; continue; }
+                if (!(un[e] > p->lo[d] && un[e] < p->hi[d])) bz[e] = 0.0;
+                bdp[e] = bz[e];
+            }
+        /* Delta p_i = (1/rho0) sum_j (lambda_i + lambda_j) grad W(z_i - z_j) */
+        for (int32_t i = 0; i < n; ++i) {
+            if (lev[i] <= k) continue;
+            const double *bi = bdp + 3 * (size_t)i;
+            for (int64_t q = off[i]; q < off[i + 1]; ++q) {
+                int32_t j = ids[q];
+                double d[3], gw[3], H[9];
+                for (int a = 0; a < 3; ++a) d[a] = zk[3 * (size_t)i + a] - zk[3 * (size_t)j + a];
+                orc_spiky_grad(d, p->h, gw);
+                orc_spiky_hess(d, p->h, H);
+                double dl = (bi[0] * gw[0] + bi[1] * gw[1] + bi[2] * gw[2]) / rho0;
+                bl[i] += dl;
+                bl[j] += dl;
+                double s = (lk[i] + lk[j]) / rho0;
+                double t[3] = {0.0, 0.0, 0.0};
+                mat_vec_add(H, bi, s, t);
+                for (int a = 0; a < 3; ++a) {
+                    bz[3 * (size_t)i + a] += t[a];
+                    bz[3 * (size_t)j + a] -= t[a];
+                }
+            }
+        }
+        /* lambda_i = -C_i / (S_i + eps) of the particles active at k: the
+         * adjoint collected over every later iteration that used this value
+         * is spent here */
+        for (int32_t i = 0; i < n; ++i) {
+            if (lev[i] <= k) continue;
+            const double C = Cv[(size_t)k * nn + i], S = Sv[(size_t)k * nn + i];
+            const double bC = -bl[i] / (S + p->eps);
+            const double bS = bl[i] * C / ((S + p->eps) * (S + p->eps));
+            bl[i] = 0.0;
+            /* C_i = rho_i / rho0 - 1, rho_i = m W(0) + m sum_j W(z_i - z_j);
+             * S_i = (1/m) (|G_i|^2 + sum_j |g_ij|^2), G_i = (m/rho0) sum_j grad W_ij,
+             * g_ij = -(m/rho0) grad W_ij */
+            double G[3] = {0.0, 0.0, 0.0};
+            for (int64_t q = off[i]; q < off[i + 1]; ++q) {
+                int32_t j = ids[q];
+                double d[3], gw[3];
+                for (int a = 0; a < 3; ++a) d[a] = zk[3 * (size_t)i + a] - zk[3 * (size_t)j + a];
+                orc_spiky_grad(d, p->h, gw);
+                for (int a = 0; a < 3; ++a) G[a] += m / rho0 * gw[a];
+            }
+            for (int64_t q = off[i]; q < off[i + 1]; ++q) {
+                int32_t j = ids[q];
+                double d[3], gw[3], gp[3], H[9];
+                for (int a = 0; a < 3; ++a) d[a] = zk[3 * (size_t)i + a] - zk[3 * (size_t)j + a];
+                orc_spiky_grad(d, p->h, gw);
+                orc_spiky_hess(d, p->h, H);
+                poly6_grad(d, p->h, gp);
+                /* adjoint of grad W_ij: from G_i and from g_ij */
+                double bg[3];
+                for (int a = 0; a < 3; ++a) {
+                    double gij = -m / rho0 * gw[a];
+                    bg[a] = (m / rho0) * (2.0 * bS * G[a] / m) - (m / rho0) * (2.0 * bS * gij / m);
+                }
+                double t[3] = {0.0, 0.0, 0.0};
+                mat_vec_add(H, bg, 1.0, t);
+                for (int a = 0; a < 3; ++a) {
+                    double c = bC * m / rho0 * gp[a];
+                    bz[3 * (size_t)i + a] += t[a] + c;
+                    bz[3 * (size_t)j + a] -= t[a] + c;
+                }
+            }
+        }
+    }
+    /* prediction: z^0 = clamp(x + dt (v + dt g)) */
+    for (int32_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            size_t e = 3 * (size_t)i + d;
+            double b = (u[e] > p->lo[d] && u[e] < p->hi[d]) ? bz[e] : 0.0;
+            gx[e] += b;
+            gv[e] = dt * b;
+        }
+done:
+    free(z); free(u); free(lam); free(Cv); free(Sv); free(bz); free(bdp); free(bl);
     return rc;
 }
 
@@ -509,7 +703,7 @@ int orc_pbf_step(const orc_params *p, int32_t iters, double *x, double *v)
     for (int32_t it = 0; it < iters; ++it) {
 #pragma omp parallel for schedule(dynamic, 256)
         for (int32_t i = 0; i < n; ++i)
-            lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL);
+            lam[i] = lambda_of(p, xs, i, ids + off[i], off[i + 1] - off[i], NULL, NULL);
 #pragma omp parallel for schedule(dynamic, 256)
         for (int32_t i = 0; i < n; ++i)
             delta_p_of(p, xs, lam, i, ids + off[i], off[i + 1] - off[i], dp + 3 * (int64_t)i);
