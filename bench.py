@@ -31,11 +31,11 @@ sys.path.insert(0, str(ROOT))
 METRIC = "particle-iterations/s and ms/step at 1M particles, APBF vs PBF(N=10)"
 
 # FP32 operations per (active particle, neighbour) pair as written in the
-# kernels: lambda pass 27 (difference 3, |d|^2 5, poly6 term 4, rsqrt and
-# r 2, spiky factor 4, gradient sum 6, squared norm 3); update pass 22
-# (difference 3, |d|^2 5, rsqrt and r 2, spiky factor 4, lambda sum and
-# scale 2, correction sum 6).
-FLOP_PER_PAIR = {"lambda": 27.0, "update": 22.0}
+# kernels (an FMA counts 2, max/select 0): lambda pass 26 (difference 3,
+# |d|^2 5, poly6 term 4, rsqrt and r 2, spiky factor 3, gradient sum 6,
+# squared norm 3); update pass 21 (difference 3, |d|^2 5, rsqrt and r 2,
+# spiky factor and lambda sum 5, correction sum 6).
+FLOP_PER_PAIR = {"lambda": 26.0, "update": 21.0}
 # compulsory HBM bytes per active particle: lambda reads x* (16) and
 # writes lambda (4); update reads x* and lambda (16 + 4) and writes x* (16)
 BYTES_PER_ACTIVE = {"lambda": 20.0, "update": 36.0}
@@ -205,10 +205,105 @@ def run_batch(args, torch, stream):
     }
 
 
+def run_rollout(args, torch, stream):
+    """The differentiable-rollout workload: 32,768 particles (32^3 lattice),
+    N = 6, dt = 1/120, 20 steps, loss = mean squared distance of the final
+    positions to a seeded target cloud, gradient with respect to the initial
+    (x, v) by the library's reverse mode with checkpoints every 5 steps.
+    Reports the wall time of the reverse pass against that of the forward
+    rollout (with checkpoints) and of 20 plain graph-launched steps."""
+    import scenes
+    from paper_1608_04721_amd import Sim
+
+    sc = scenes.rollout_32k()
+    T, every = int(sc.steps), 5
+    reps = max(1, args.steps // 20)
+    n = sc.n
+    tgt = sc.target.astype(np.float32)
+    zero = np.zeros((n, 3), np.float32)
+    with Sim(sc, stream=stream) as sim:
+        x0, v0, _ = sim.get_state()
+        sim.set_graph(True)
+        # warm-up: one of each
+        sim.step(T)
+        sim.sync()
+        sim.set_state(x0, v0)
+        sim.rollout_forward(T, every)
+        sim.sync()
+        g = ((2.0 / n) * (sim.positions() - tgt)).astype(np.float32)
+        sim.rollout_backward(g, zero)
+        t_plain, t_fwd, t_bwd = [], [], []
+        for _ in range(reps):
+            sim.set_state(x0, v0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(T)
+            sim.sync()
+            t_plain.append(time.perf_counter() - t0)
+            sim.set_state(x0, v0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.rollout_forward(T, every)
+            sim.sync()
+            t_fwd.append(time.perf_counter() - t0)
+            g = ((2.0 / n) * (sim.positions() - tgt)).astype(np.float32)
+            t0 = time.perf_counter()
+            gx, gv = sim.rollout_backward(g, zero)
+            t_bwd.append(time.perf_counter() - t0)
+        loss = float(np.mean(np.sum((sim.positions().astype(np.float64) - tgt) ** 2, axis=1)))
+    plain, fwd, bwd = (1e3 * float(np.median(a)) for a in (t_plain, t_fwd, t_bwd))
+    return {
+        "metric": "adjoint/forward wall-time ratio, 32,768-particle 20-step differentiable rollout",
+        "value": round(bwd / fwd, 4), "unit": "x", "n_gpus": 1, "steps": reps * T,
+        "warmup": T, "ms_per_step": round((fwd + bwd) / T, 4), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rollout_32k: 32,768 particles (32^3 lattice), N=6, dt=1/120, "
+                               "20 steps, loss = mean squared distance to a seeded target cloud, "
+                               "checkpoints every 5 steps", "particles": n, "steps": T,
+                   "ckpt_every": every, "repeats": reps},
+        "ms_forward_plain_graph": round(plain, 3),
+        "ms_rollout_forward": round(fwd, 3),
+        "ms_rollout_backward": round(bwd, 3),
+        "backward_vs_plain_forward": round(bwd / plain, 4),
+        "loss": loss, "grad_v_norm": float(np.linalg.norm(gv)),
+    }
+
+
+def run_traffic(args, torch, stream):
+    """A short run for hardware-counter passes (rocprofv3 --pmc FETCH_SIZE,
+    then WRITE_SIZE): first a plain device copy of 256 MiB, three times,
+    whose counter readings calibrate the counters against a known byte
+    count; then the tank workload, 2 warm-up steps and 3 steps, with direct
+    launches so every kernel is a dispatch of its own."""
+    import scenes
+    from paper_1608_04721_amd import Sim
+
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            dst.copy_(src)
+    torch.cuda.synchronize()
+    sc = scenes.tank_1m()
+    with Sim(sc, stream=stream) as sim:
+        sim.set_graph(False)
+        sim.step(2)
+        sim.sync()
+        sim.step(3)
+        sim.sync()
+        st = sim.stats()
+    return {"workload": "traffic", "copy_bytes": nbytes, "steps": 3,
+            "particle_iterations_last_step": st["particle_iterations"],
+            "neighbour_pairs_last_step": st["neighbour_pairs"]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--workload", choices=("tank", "batch"), default="tank",
-                    help="tank: the 1M-particle headline line (default); batch: 64 scenes")
+    ap.add_argument("--workload", choices=("tank", "batch", "rollout", "traffic"), default="tank",
+                    help="tank: the 1M-particle headline line (default); batch: 64 scenes; "
+                         "rollout: reverse-mode cost on the 32k-particle rollout; traffic: "
+                         "short run for hardware-counter passes")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
@@ -232,6 +327,12 @@ def main(argv=None):
     stream = torch.cuda.Stream()  # default priority
     if args.workload == "batch":
         print(json.dumps(run_batch(args, torch, stream)), flush=True)
+        return 0
+    if args.workload == "rollout":
+        print(json.dumps(run_rollout(args, torch, stream)), flush=True)
+        return 0
+    if args.workload == "traffic":
+        print(json.dumps(run_traffic(args, torch, stream)), flush=True)
         return 0
     sc = scenes.tank_1m()
     steps, warm = args.steps, args.warmup

@@ -270,3 +270,64 @@ class Sim:
         v = _f32(v).reshape(-1)
         self._check(self._lib.pbf_set_state(self._ctx, x.ctypes.data, v.ctypes.data, int(step)),
                     "pbf_set_state")
+
+    # ------------------------------------------------ differentiable rollout
+    def rollout_forward(self, n_steps: int, ckpt_every: int = 1):
+        """Advance n_steps steps, checkpointing every ckpt_every steps for a
+        later rollout_backward."""
+        self._check(self._lib.pbf_rollout_forward(self._ctx, int(n_steps), int(ckpt_every)),
+                    "pbf_rollout_forward")
+
+    def rollout_backward(self, dl_dx, dl_dv, out_x=None, out_v=None):
+        """Adjoints of the rollout's initial (x, v) from those of its final
+        state (ID order, (n, 3)).  Host arrays give host arrays; CUDA tensors
+        (with CUDA tensors out_x, out_v to fill) stay on the device."""
+        if _is_tensor(dl_dx) and dl_dx.is_cuda:
+            gx, gv = dl_dx.contiguous(), dl_dv.contiguous()
+            if out_x is None or out_v is None:
+                raise ValueError("device adjoints need device out_x and out_v")
+            self._check(self._lib.pbf_rollout_backward(self._ctx, gx.data_ptr(), gv.data_ptr(),
+                                                       out_x.data_ptr(), out_v.data_ptr(), 1),
+                        "pbf_rollout_backward")
+            return out_x, out_v
+        gx, gv = _f32(dl_dx).reshape(-1), _f32(dl_dv).reshape(-1)
+        ox = np.empty(3 * self.n, np.float32)
+        ov = np.empty(3 * self.n, np.float32)
+        self._check(self._lib.pbf_rollout_backward(self._ctx, gx.ctypes.data, gv.ctypes.data,
+                                                   ox.ctypes.data, ov.ctypes.data, 0),
+                    "pbf_rollout_backward")
+        return ox.reshape(-1, 3), ov.reshape(-1, 3)
+
+
+def rollout(sim: Sim, x0, v0, n_steps: int, ckpt_every: int = 1):
+    """Differentiable rollout for PyTorch: sets sim's state to the CUDA
+    tensors (x0, v0) ((n, 3) float32, ID order), advances n_steps steps and
+    returns the final (x, v) as new tensors; backward() calls the library's
+    reverse mode (levels, neighbour sets and wall contacts of every step held
+    fixed)."""
+    import torch
+
+    class _Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, v):
+            xc, vc = x.detach(), v.detach()
+            sim.set_state(xc.cpu().numpy(), vc.cpu().numpy())  # host entry point
+            sim.rollout_forward(n_steps, ckpt_every)
+            xo = torch.empty((sim.n, 3), device=x.device, dtype=torch.float32)
+            vo = torch.empty_like(xo)
+            sim.positions(out=xo)
+            sim.velocities(out=vo)
+            sim.sync()  # the copies ran on the library's stream
+            return xo, vo
+
+        @staticmethod
+        def backward(ctx, gx, gv):
+            gx = torch.zeros((sim.n, 3), device="cuda", dtype=torch.float32) if gx is None else gx
+            gv = torch.zeros((sim.n, 3), device="cuda", dtype=torch.float32) if gv is None else gv
+            ox = torch.empty((sim.n, 3), device=gx.device, dtype=torch.float32)
+            ov = torch.empty_like(ox)
+            torch.cuda.current_stream().synchronize()
+            sim.rollout_backward(gx.float(), gv.float(), ox, ov)
+            return ox, ov
+
+    return _Rollout.apply(x0, v0)

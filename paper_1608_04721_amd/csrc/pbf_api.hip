@@ -480,6 +480,7 @@ pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const fl
     AL(b.tmp_src, n);
     AL(b.tmp_id, n);
     AL(b.cell_count, (size_t)cells);
+    if (e == hipSuccess) e = hipMemset(b.cell_count, 0, sizeof(uint32_t) * std::max<size_t>(cells, 1));
     AL(b.cell_start, (size_t)cells + 1);
     AL(b.scan_part, (size_t)b.n_scan_blocks);
     AL(dtile_scene, (size_t)tiles);
@@ -937,6 +938,8 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
     // adjoint state (ID order) and the final state to restore afterwards
     float *ax = (float *)alloc(n3 * 4), *av = (float *)alloc(n3 * 4);
     float *fx = (float *)alloc(n3 * 4), *fv = (float *)alloc(n3 * 4);
+    // the recomputed steps must not count in the context's running totals
+    unsigned long long *tot = (unsigned long long *)alloc(2 * sizeof(unsigned long long));
     AdjointScratch w{};
     w.nslot = (uint32_t *)alloc((size_t)n * c->b.nbr_cap * 4);
     w.zb = (float4 *)alloc((size_t)n * 16);
@@ -947,7 +950,7 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
     w.sb = (float *)alloc((size_t)n * 4);
     std::vector<StepRecord> recs((size_t)seg_len);
     const size_t T_t = c->b.n_tiles;
-    bool ok = ax && av && fx && fv && w.nslot && w.zb && w.xb && w.dpb && w.gc && w.lb && w.sb;
+    bool ok = ax && av && fx && fv && tot && w.nslot && w.zb && w.xb && w.dpb && w.gc && w.lb && w.sb;
     for (auto &r : recs) {
         if (!ok) break;
         r.id = (uint32_t *)alloc((size_t)n * 4);
@@ -980,6 +983,8 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
             return r_;                                 \
         }                                              \
     } while (0)
+    BCHK(hipMemcpyAsync(tot, c->b.totals, 2 * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                        c->stream), "save totals");
     BCHK(hipMemcpyAsync(ax, dl_dx, n3 * 4, kin, c->stream), "gradient in");
     BCHK(hipMemcpyAsync(av, dl_dv, n3 * 4, kin, c->stream), "gradient in");
     BCHK(enqueue_unpermute(n, c->b.x[c->cur], c->b.id[c->cur], fx, 0, (uint32_t)n, c->stream), "save state");
@@ -1003,6 +1008,8 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
     // back to the final state of the rollout (storage order = ID order)
     BCHK(enqueue_load_state(n, fx, fv, c->b.id_scene, c->b.x[0], c->b.v[0], c->b.id[0], c->stream),
          "restore state");
+    BCHK(hipMemcpyAsync(c->b.totals, tot, 2 * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                        c->stream), "restore totals");
     c->cur = 0;
     c->stepped = false;
     BCHK(hipStreamSynchronize(c->stream), "stream synchronize");

@@ -21,6 +21,10 @@ constexpr int kNbrThreads = 256;   // threads of a neighbour-build tile workgrou
 constexpr int kBndWords = kStageRows * (kStageEdge + 1);  // cell bounds of the staged rows
 constexpr int kRowWords = kBndWords + kStageRows + 1;     // saved tables per tile
 constexpr int kSegOffBits = 10;    // fallback neighbour code: row << 10 | offset
+// LDS stage entry kStageCap (one past the staged particles) holds a point
+// this far away; its code pads the last group of a neighbour list
+constexpr uint32_t kFarCode = kStageCap;
+constexpr float kFar = 1e18f;
 // pmeta bit fields: level << 16 | neighbour count
 constexpr int kMetaLevel = 16;
 constexpr uint32_t kMetaCount = 0xffffu;
@@ -54,8 +58,7 @@ enum : uint32_t {
 
 // Kernel classes (launch shape and profiling unit).
 enum Kernel : int {
-    K_FILL = 0,
-    K_LOD_PREDICT,
+    K_LOD_PREDICT = 0,
     K_SCAN_REDUCE,
     K_SCAN_TOP,
     K_SCAN_APPLY,

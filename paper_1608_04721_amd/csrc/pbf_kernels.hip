@@ -31,14 +31,14 @@
 namespace pbf {
 
 const char *const kKernelNames[K_COUNT] = {
-    "fill",        "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",
-    "sort_scatter", "sort_finish", "tile_prepare", "level_count", "level_scan",
-    "level_scatter", "neighbours", "lambda",      "update",       "commit"};
+    "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
+    "sort_finish",  "tile_prepare", "level_count", "level_scan",  "level_scatter",
+    "neighbours",   "lambda",      "update",       "commit"};
 
-const int kDefaultBlock[K_COUNT] = {256,         256,          kScanBlock,   1024,
-                                    kScanBlock,  256,          256,          256,
-                                    kLevelBlock, 1024,         kLevelBlock,  kNbrThreads,
-                                    kTileThreads, kTileThreads, 256};
+const int kDefaultBlock[K_COUNT] = {256,          kScanBlock,   1024,         kScanBlock,
+                                    256,          256,          256,          kLevelBlock,
+                                    1024,         kLevelBlock,  kNbrThreads,  kTileThreads,
+                                    kTileThreads, 256};
 
 namespace {
 
@@ -113,13 +113,6 @@ __device__ __forceinline__ int dtc_level(float x, float y, float z, float cx, fl
     t = fminf(fmaxf(t, 0.f), 1.f);
     const int L = nmax - (int)floorf(t * (float)(nmax - nmin + 1));
     return min(max(L, nmin), nmax);
-}
-
-// ------------------------------------------------------------------ fill
-__global__ void k_fill(uint32_t *__restrict__ p, uint32_t n, uint32_t value)
-{
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = value;
 }
 
 // --------------------------------------------- levels + forces + prediction
@@ -230,8 +223,10 @@ __global__ void k_scan_top(uint32_t *__restrict__ part, uint32_t nb)
     }
 }
 
-__global__ void k_scan_apply(const uint32_t *__restrict__ in, uint32_t G,
-                             const uint32_t *__restrict__ part, uint32_t *__restrict__ out)
+// clear: if not null (the same array as in), each count is zeroed once read,
+// which leaves the cell histogram ready for the next step
+__global__ void k_scan_apply(const uint32_t *in, uint32_t G, const uint32_t *__restrict__ part,
+                             uint32_t *__restrict__ out, uint32_t *clear)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
     // each thread owns kScanItems consecutive cells
@@ -244,6 +239,11 @@ __global__ void k_scan_apply(const uint32_t *__restrict__ in, uint32_t G,
         uint32_t e = base + q;
         vals[q] = e < G ? in[e] : 0u;
         sum += vals[q];
+    }
+    if (clear) {
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q)
+            if (base + q < G) clear[base + q] = 0u;
     }
     uint32_t run = part[blockIdx.x] + block_exclusive_sum(sum, lds, nullptr);
 #pragma unroll
@@ -379,11 +379,13 @@ __device__ bool tile_tables(const TileLoc &t, const uint32_t *__restrict__ cell_
     return tb.base[kStageRows] <= (uint32_t)kStageCap;
 }
 
-// copy the staged rows of `src` into LDS (all threads; ends with a barrier)
+// copy the staged rows of `src` into LDS, plus the far-away entry at
+// kFarCode that pads neighbour groups (all threads; ends with a barrier)
 __device__ __forceinline__ void tile_stage(const TileTables &tb, const float4 *__restrict__ src,
                                            float4 *__restrict__ stage)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) stage[kFarCode] = make_float4(kFar, kFar, kFar, 0.f);
     for (int r = wave; r < kStageRows; r += nw) {
         const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0, b0 = tb.base[r];
         for (uint32_t e = lane; e < len; e += 64) stage[b0 + e] = src[g0 + e];
@@ -515,26 +517,23 @@ __global__ void k_level_scatter(uint32_t m, const uint8_t *__restrict__ lvl,
 // the stage did not fit in LDS.  Codes are packed eight to a 16-byte group,
 // groups stored group-major (nbr[g * n + p]): one store per eight
 // neighbours here, fully coalesced loads in the solver passes.
-__global__ __launch_bounds__(kNbrThreads) void k_neighbours(
-    const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
-    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
-    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ cell_start,
-    const float4 *__restrict__ xs, const uint8_t *__restrict__ lvl, int64_t n, int cap,
-    uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta, uint32_t *__restrict__ pslot,
-    uint32_t *__restrict__ rows, uint32_t *__restrict__ err)
+// The neighbour list of every own particle of one tile.  FITS: the stage is
+// in LDS and codes are stage indices; the unused codes of a particle's last
+// group point at the stage's far-away entry, so the solver passes read whole
+// groups without tests.
+//
+// Each window is scanned in chunks of 32 candidates, four candidates per
+// round (their loads issued together) into a 32-bit hit mask; the hits then
+// become codes in candidate order.  Codes collect four at a time in a 64-bit
+// word; every eighth code stores one 16-byte group.
+template <bool FITS>
+__device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const float4 *__restrict__ stage,
+                                                    const float4 *__restrict__ xs, float h2, uint32_t p0,
+                                                    int64_t n, int cap, const uint8_t *__restrict__ lvl,
+                                                    uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta,
+                                                    uint32_t *__restrict__ pslot)
 {
-    __shared__ TileTables tb;
-    __shared__ float4 stage[kStageCap];
-    if (blockIdx.x >= tile_ge[1]) return;  // empty tiles are not listed before this bound
-    const uint32_t tile = tile_order[blockIdx.x];
-    const TileLoc t = tile_locate(tile, tile_scene, sc);
-    const bool fits = tile_tables(t, cell_start, tb);
-    // keep the tables for the solver passes of this step
-    for (int e = threadIdx.x; e < kRowWords; e += blockDim.x)
-        rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
-    if (fits) tile_stage(tb, xs, stage);
-    const float h2 = t.S->h2;
-    const uint32_t p0 = tile_start[tile], nown = tb.own[kOwnRows];
+    const uint32_t nown = tb.own[kOwnRows];
     uint32_t bad = 0;
     for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
         int o = 0;
@@ -544,59 +543,111 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbours(
         const uint32_t i = tb.bnd[r][1] + (pl - tb.own[o]);
         int lx = 1;
         while (lx < kTileEdge && tb.bnd[r][lx + 1] <= i) ++lx;  // x-cell of i, 1..kTileEdge
-        const float4 xi = fits ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
+        const float4 xi = FITS ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
         const size_t p = p0 + pl;
-        uint32_t cnt = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;  // eight pending codes
+        uint32_t cnt = 0;
+        uint64_t acc = 0, half = 0;  // codes cnt & ~3 .. cnt - 1; first half of the group
+        const uint32_t cap8 = ((uint32_t)cap + 7u) & ~7u;  // codes that have room
+        auto put = [&](uint32_t code) {
+            acc |= (uint64_t)code << ((cnt & 3u) * 16u);
+            ++cnt;
+            if ((cnt & 3u) == 0) {
+                if (cnt & 4u) {
+                    half = acc;
+                } else if (cnt <= cap8) {
+                    nbr[(size_t)((cnt >> 3) - 1) * n + p] =
+                        make_uint4((uint32_t)half, (uint32_t)(half >> 32), (uint32_t)acc,
+                                   (uint32_t)(acc >> 32));
+                }
+                acc = 0;
+            }
+        };
 #pragma unroll 1
         for (int w = 0; w < 9; ++w) {
             const int r2 = (sz + w / 3 - 1) * kStageEdge + (sy + w % 3 - 1);
             const uint32_t g0 = tb.bnd[r2][0];
             const uint32_t ja = tb.bnd[r2][lx - 1], len = tb.bnd[r2][lx + 2] - ja;
             const uint32_t l0 = tb.base[r2] + (ja - g0);
-            for (uint32_t c0 = 0; c0 < len; c0 += 64) {
-                // distance test of up to 64 candidates into a bit mask ...
-                const uint32_t cl = min(len - c0, 64u);
-                uint64_t m = 0;
-                for (uint32_t c = 0; c < cl; ++c) {
-                    const float4 xj = fits ? stage[l0 + c0 + c] : xs[ja + c0 + c];
-                    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                    if (dx * dx + dy * dy + dz * dz < h2) m |= 1ull << c;
+            for (uint32_t c0 = 0; c0 < len; c0 += 32) {
+                // distance test of up to 32 candidates into a bit mask ...
+                const uint32_t cl = min(len - c0, 32u);
+                uint32_t m = 0;
+                for (uint32_t c = 0; c < cl; c += 4) {
+                    float4 xj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        // past the window's end: another staged particle or the
+                        // far entry, masked below; never past the stage
+                        xj[u] = FITS ? stage[min(l0 + c0 + c + u, kFarCode)]
+                                     : xs[min((int64_t)(ja + c0 + c + u), n - 1)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
+                        m |= (dx * dx + dy * dy + dz * dz < h2) ? (1u << (c + u)) : 0u;
+                    }
                 }
-                if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1ull << (i - ja - c0));  // not itself
+                if (cl < 32u) m &= (1u << cl) - 1u;
+                if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1u << (i - ja - c0));  // not itself
                 // ... then its hits become codes, in candidate order
                 while (m) {
-                    const uint32_t c = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
-                    m &= m - 1ull;
-                    uint32_t code;
-                    if (fits) {
-                        code = l0 + c;
+                    const uint32_t c = c0 + (uint32_t)(__ffs(m) - 1);
+                    m &= m - 1u;
+                    if (FITS) {
+                        put(l0 + c);
                     } else {
                         const uint32_t off = ja + c - g0;
                         if (off >= (1u << kSegOffBits)) bad |= ERR_CELL_CAP;
-                        code = ((uint32_t)r2 << kSegOffBits) | (off & ((1u << kSegOffBits) - 1));
-                    }
-                    const uint32_t v = code << ((cnt & 1u) * 16u);
-                    const uint32_t wd = (cnt >> 1) & 3u;
-                    b0 |= wd == 0 ? v : 0u;
-                    b1 |= wd == 1 ? v : 0u;
-                    b2 |= wd == 2 ? v : 0u;
-                    b3 |= wd == 3 ? v : 0u;
-                    ++cnt;
-                    if ((cnt & 7u) == 0) {
-                        if (cnt <= (uint32_t)cap)
-                            nbr[(size_t)((cnt >> 3) - 1) * n + p] = make_uint4(b0, b1, b2, b3);
-                        b0 = b1 = b2 = b3 = 0;
+                        put(((uint32_t)r2 << kSegOffBits) | (off & ((1u << kSegOffBits) - 1)));
                     }
                 }
             }
         }
-        if ((cnt & 7u) && cnt <= (uint32_t)cap) nbr[(size_t)(cnt >> 3) * n + p] = make_uint4(b0, b1, b2, b3);
         if (cnt > (uint32_t)cap) {
             bad |= ERR_NEIGHBOUR_CAP;
             cnt = (uint32_t)cap & ~7u;  // only whole stored groups are valid
+        } else if (cnt & 7u) {
+            const uint32_t keep = cnt;
+            if (FITS) {
+                while (cnt & 7u) put(kFarCode);  // pad; stores the group
+            } else {
+                const uint64_t lo = (cnt & 4u) ? half : acc, hi = (cnt & 4u) ? acc : 0;
+                nbr[(size_t)(cnt >> 3) * n + p] =
+                    make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+            }
+            cnt = keep;
         }
         pslot[p] = i;
         pmeta[p] = ((uint32_t)lvl[i] << kMetaLevel) | cnt;
+    }
+    return bad;
+}
+
+__global__ __launch_bounds__(kNbrThreads) void k_neighbours(
+    const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
+    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ cell_start,
+    const float4 *__restrict__ xs, const uint8_t *__restrict__ lvl, int64_t n, int cap,
+    uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta, uint32_t *__restrict__ pslot,
+    uint32_t *__restrict__ rows, uint32_t *__restrict__ err)
+{
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageCap + 1];
+    if (blockIdx.x >= tile_ge[1]) return;  // empty tiles are not listed before this bound
+    const uint32_t tile = tile_order[blockIdx.x];
+    const TileLoc t = tile_locate(tile, tile_scene, sc);
+    const bool fits = tile_tables(t, cell_start, tb);
+    // keep the tables for the solver passes of this step
+    for (int e = threadIdx.x; e < kRowWords; e += blockDim.x)
+        rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
+    const float h2 = t.S->h2;
+    const uint32_t p0 = tile_start[tile];
+    uint32_t bad;
+    if (fits) {
+        tile_stage(tb, xs, stage);
+        bad = tile_neighbours<true>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot);
+    } else {
+        bad = tile_neighbours<false>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot);
     }
     if (bad) atomicOr(err, bad);
 }
@@ -620,34 +671,96 @@ __device__ __forceinline__ bool stage_rows(const uint32_t *__restrict__ rows, ui
 }
 
 // Walk the neighbour list of particle p in stored order, calling f(position
-// and lambda of the neighbour); codes are read eight at a time.
-template <class F>
-__device__ __forceinline__ void for_each_neighbour(const TileTables &tb, bool fits,
+// and lambda of the neighbour); codes are read eight at a time.  FITS: every
+// code of a stored group is an LDS index (padding codes name the far-away
+// entry, which no test admits); otherwise codes are row << 10 | offset into
+// `src` and the tail of the last group is skipped.
+template <bool FITS, class F>
+__device__ __forceinline__ void for_each_neighbour(const TileTables &tb,
                                                    const float4 *__restrict__ stage,
                                                    const float4 *__restrict__ src,
                                                    const uint4 *__restrict__ nbr, int64_t n,
                                                    size_t p, uint32_t cnt, F &&f)
 {
-    auto get = [&](uint32_t c) -> float4 {
-        return fits ? stage[c] : src[tb.bnd[c >> kSegOffBits][0] + (c & ((1u << kSegOffBits) - 1))];
-    };
+    // the next group's codes are loaded while this group is evaluated; the
+    // index is clamped to the last group (group 0 exists for every p), so
+    // every load is unconditional
+    const uint32_t last = cnt ? (cnt - 1u) >> 3 : 0u;
+    uint4 v = nbr[p];
     for (uint32_t q = 0; q < cnt; q += 8) {
-        const uint4 v = nbr[(size_t)(q >> 3) * n + p];
+        const uint4 vn = nbr[(size_t)min((q >> 3) + 1u, last) * n + p];
         const uint32_t cc[8] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16,
                                 v.z & 0xffffu, v.z >> 16, v.w & 0xffffu, v.w >> 16};
-        const uint32_t m = min(cnt - q, 8u);
+        v = vn;
         float4 xj[8];
+        if (FITS) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xj[u] = (uint32_t)u < m ? get(cc[u]) : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int u = 0; u < 8; ++u) xj[u] = stage[cc[u]];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if ((uint32_t)u < m) f(xj[u]);
+            for (int u = 0; u < 8; ++u) f(xj[u]);
+        } else {
+            const uint32_t m = min(cnt - q, 8u);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                xj[u] = (uint32_t)u < m
+                            ? src[tb.bnd[cc[u] >> kSegOffBits][0] + (cc[u] & ((1u << kSegOffBits) - 1))]
+                            : make_float4(kFar, kFar, kFar, 0.f);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) f(xj[u]);
+        }
     }
 }
 
 // ------------------------------------------------ solver iteration k
-// lambda_i for the active particles of the tile (Eqs. 4-6), written to
-// xs[i].w; neighbours read only xyz of the same buffer.
+// Pair terms are evaluated without branches: outside the radius (and for the
+// far-away padding entry) the clamped factors are zero.  1/r is the hardware
+// reciprocal square root (about 1 ulp) of max(r^2, kTinyR2): coincident
+// particles (r = 0, d = 0) then give a finite factor times d = 0, so no
+// gradient, as for the exact kernel; distinct float32 positions are never
+// that close.  The constant factor -c_grad of the spiky gradient is applied
+// once per particle instead of once per pair.
+constexpr float kTinyR2 = 1e-20f;
+
+// lambda_i for the active own particles of a tile (Eqs. 4-6)
+template <bool FITS>
+__device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const TileTables &tb,
+                                            const float4 *__restrict__ stage, float4 *__restrict__ xs,
+                                            int64_t n, const uint4 *__restrict__ nbr,
+                                            const uint32_t *__restrict__ pmeta,
+                                            const uint32_t *__restrict__ pslot, uint32_t p0,
+                                            uint32_t nown)
+{
+    const float h = S.h, h2 = S.h2, cg = S.c_grad, h6 = S.h6, crho = S.c_rho, cs = S.c_s,
+                eps = S.eps;
+    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+        const size_t p = p0 + pl;
+        const uint32_t meta = pmeta[p];
+        if ((int)(meta >> kMetaLevel) <= k) continue;
+        const uint32_t i = pslot[p];
+        const float4 xi = xs[i];
+        float sum6 = h6;  // the particle itself: (h^2 - 0)^3
+        float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
+        for_each_neighbour<FITS>(tb, stage, xs, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float w = fmaxf(h2 - r2, 0.f);
+            sum6 += w * w * w;
+            const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, kTinyR2));
+            const float hr = fmaxf(h - r2 * ir, 0.f);
+            const float q = hr * hr * ir;  // grad W = -c_grad q d
+            gx += q * dx;
+            gy += q * dy;
+            gz += q * dz;
+            g2 += q * q * r2;
+        });
+        const float C = crho * sum6 - 1.f;
+        const float denom = cs * cg * cg * (gx * gx + gy * gy + gz * gz + g2) + eps;
+        xs[i].w = -C / denom;
+    }
+}
+
+// lambda_i of the tile's active particles, written to xs[i].w; neighbours
+// read only xyz of the same buffer.
 __global__ __launch_bounds__(kTileThreads) void k_lambda(
     int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
@@ -657,67 +770,32 @@ __global__ __launch_bounds__(kTileThreads) void k_lambda(
     const uint32_t *__restrict__ pslot)
 {
     __shared__ TileTables tb;
-    __shared__ float4 stage[kStageCap];
+    __shared__ float4 stage[kStageCap + 1];
     if (blockIdx.x >= tile_ge[k + 1]) return;
     const uint32_t tile = tile_order[blockIdx.x];
     const SceneDev &S = sc[tile_scene[tile]];
-    const bool fits = stage_rows(rows, tile, xs, tb, stage);
-    const float h = S.h, h2 = S.h2, cg = S.c_grad, h6 = S.h6, crho = S.c_rho, cs = S.c_s,
-                eps = S.eps;
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
-    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
-        const size_t p = p0 + pl;
-        const uint32_t meta = pmeta[p];
-        if ((int)(meta >> kMetaLevel) <= k) continue;
-        const uint32_t i = pslot[p];
-        const float4 xi = xs[i];
-        float sum6 = h6;  // the particle itself: (h^2 - 0)^3
-        float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
-        for_each_neighbour(tb, fits, stage, xs, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
-            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < h2) {
-                const float w = h2 - r2;
-                sum6 += w * w * w;
-                if (r2 > 0.f) {
-                    const float ir = rsqrtf(r2);
-                    const float hr = h - r2 * ir;
-                    const float f = -cg * hr * hr * ir;  // grad W = f d
-                    gx += f * dx;
-                    gy += f * dy;
-                    gz += f * dz;
-                    g2 += f * f * r2;
-                }
-            }
-        });
-        const float C = crho * sum6 - 1.f;
-        const float denom = cs * (gx * gx + gy * gy + gz * gz + g2) + eps;
-        xs[i].w = -C / denom;
-    }
+    if (stage_rows(rows, tile, xs, tb, stage))
+        tile_lambda<true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown);
+    else
+        tile_lambda<false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown);
 }
 
-// Delta p_i for the active particles of the tile (Eq. 7) with the wall
-// contact (clamp), written to the other buffer (Jacobi).  Particles that
-// finished with this iteration (N_i == k) copy position and lambda across,
-// so that both buffers hold their final values from now on.
-__global__ __launch_bounds__(kTileThreads) void k_update(
-    int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
-    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
-    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
-    const uint32_t *__restrict__ rows, const float4 *__restrict__ xs_in,
-    float4 *__restrict__ xs_out, int64_t n, const uint4 *__restrict__ nbr,
-    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot)
+// Delta p_i (Eq. 7) with the wall contact (clamp) for the active own
+// particles of a tile
+template <bool FITS>
+__device__ __forceinline__ void tile_update(int k, const SceneDev &S, const TileTables &tb,
+                                            const float4 *__restrict__ stage,
+                                            const float4 *__restrict__ xs_in,
+                                            float4 *__restrict__ xs_out, int64_t n,
+                                            const uint4 *__restrict__ nbr,
+                                            const uint32_t *__restrict__ pmeta,
+                                            const uint32_t *__restrict__ pslot, uint32_t p0,
+                                            uint32_t nown)
 {
-    __shared__ TileTables tb;
-    __shared__ float4 stage[kStageCap];
-    if (blockIdx.x >= tile_ge[k > 1 ? k : 1]) return;  // tiles with a particle of level >= k
-    const uint32_t tile = tile_order[blockIdx.x];
-    const SceneDev &S = sc[tile_scene[tile]];
-    const bool fits = stage_rows(rows, tile, xs_in, tb, stage);
-    const float h = S.h, h2 = S.h2, cg = S.c_grad, sr = S.inv_rho0;
+    const float h = S.h, cg = S.c_grad, sr = S.inv_rho0;
     const float lo0 = S.lo[0], lo1 = S.lo[1], lo2 = S.lo[2];
     const float hi0 = S.hi[0], hi1 = S.hi[1], hi2 = S.hi[2];
-    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
     for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t meta = pmeta[p];
@@ -731,21 +809,44 @@ __global__ __launch_bounds__(kTileThreads) void k_update(
         }
         const float li = xi.w;
         float px = 0.f, py = 0.f, pz = 0.f;
-        for_each_neighbour(tb, fits, stage, xs_in, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+        for_each_neighbour<FITS>(tb, stage, xs_in, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < h2 && r2 > 0.f) {
-                const float ir = rsqrtf(r2);
-                const float hr = h - r2 * ir;
-                const float f = -cg * hr * hr * ir * (li + xj.w);
-                px += f * dx;
-                py += f * dy;
-                pz += f * dz;
-            }
+            const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, kTinyR2));
+            const float hr = fmaxf(h - r2 * ir, 0.f);
+            const float f = hr * hr * ir * (li + xj.w);  // (lambda_i + lambda_j) grad W = -c_grad f d
+            px += f * dx;
+            py += f * dy;
+            pz += f * dz;
         });
-        xs_out[i] = make_float4(clampf(xi.x + px * sr, lo0, hi0), clampf(xi.y + py * sr, lo1, hi1),
-                                clampf(xi.z + pz * sr, lo2, hi2), li);
+        const float s = -cg * sr;
+        xs_out[i] = make_float4(clampf(xi.x + px * s, lo0, hi0), clampf(xi.y + py * s, lo1, hi1),
+                                clampf(xi.z + pz * s, lo2, hi2), li);
     }
+}
+
+// Corrections of the tile's active particles, written to the other buffer
+// (Jacobi).  Particles that finished with this iteration (N_i == k) copy
+// position and lambda across, so that both buffers hold their final values
+// from now on.
+__global__ __launch_bounds__(kTileThreads) void k_update(
+    int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
+    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
+    const uint32_t *__restrict__ rows, const float4 *__restrict__ xs_in,
+    float4 *__restrict__ xs_out, int64_t n, const uint4 *__restrict__ nbr,
+    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot)
+{
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageCap + 1];
+    if (blockIdx.x >= tile_ge[k > 1 ? k : 1]) return;  // tiles with a particle of level >= k
+    const uint32_t tile = tile_order[blockIdx.x];
+    const SceneDev &S = sc[tile_scene[tile]];
+    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    if (stage_rows(rows, tile, xs_in, tb, stage))
+        tile_update<true>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown);
+    else
+        tile_update<false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown);
 }
 
 // --------------------------------------------- velocity and position update
@@ -796,13 +897,14 @@ inline unsigned blocks_for(int64_t n, int block)
         if (e_ != hipSuccess) return e_;                                        \
     } while (0)
 
-static hipError_t enqueue_scan(const uint32_t *in, uint32_t count, uint32_t *part, uint32_t *out,
-                               hipStream_t s, Timer *tm)
+static hipError_t enqueue_scan(uint32_t *in, uint32_t count, uint32_t *part, uint32_t *out,
+                               bool clear_in, hipStream_t s, Timer *tm)
 {
     const unsigned nb = blocks_for(count, kScanBlock * kScanItems);
     LAUNCH(K_SCAN_REDUCE, nb, kScanBlock, k_scan_reduce, in, count, part);
     LAUNCH(K_SCAN_TOP, 1, 1024, k_scan_top, part, nb);
-    LAUNCH(K_SCAN_APPLY, nb, kScanBlock, k_scan_apply, in, count, part, out);
+    LAUNCH(K_SCAN_APPLY, nb, kScanBlock, k_scan_apply, in, count, part, out,
+           clear_in ? in : nullptr);
     return hipSuccess;
 }
 
@@ -828,11 +930,13 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     const int *bs = ls.block;
     hipError_t e;
 
-    LAUNCH(K_FILL, blocks_for(G, bs[K_FILL]), bs[K_FILL], k_fill, b.cell_count, G, 0u);
+    // cell_count is all zero here: cleared at creation, and by the cell scan
+    // of every step once it has read the counts
     LAUNCH(K_LOD_PREDICT, blocks_for(n, bs[K_LOD_PREDICT]), bs[K_LOD_PREDICT], k_lod_predict, n,
            b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.xs_pred, b.lvl[cur],
            b.key_pre, b.ticket, b.cell_count, b.level_part);
-    if ((e = enqueue_scan(b.cell_count, G, b.scan_part, b.cell_start, s, tm)) != hipSuccess) return e;
+    if ((e = enqueue_scan(b.cell_count, G, b.scan_part, b.cell_start, true, s, tm)) != hipSuccess)
+        return e;
     LAUNCH(K_SORT_SCATTER, blocks_for(n, bs[K_SORT_SCATTER]), bs[K_SORT_SCATTER], k_sort_scatter,
            n, b.key_pre, b.ticket, b.cell_start, b.id[cur], b.tmp_src, b.tmp_id);
     LAUNCH(K_SORT_FINISH, blocks_for(n, bs[K_SORT_FINISH]), bs[K_SORT_FINISH], k_sort_finish, n,
@@ -842,7 +946,8 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     LAUNCH(K_TILE_PREPARE, blocks_for((int64_t)T * 64, bs[K_TILE_PREPARE]), bs[K_TILE_PREPARE],
            k_tile_prepare, T, b.scenes, b.tile_scene, b.cell_start, b.lvl[nxt], b.tile_count,
            b.tile_lvl);
-    if ((e = enqueue_scan(b.tile_count, T, b.scan_part, b.tile_start, s, tm)) != hipSuccess) return e;
+    if ((e = enqueue_scan(b.tile_count, T, b.scan_part, b.tile_start, false, s, tm)) != hipSuccess)
+        return e;
     LAUNCH(K_LEVEL_COUNT, b.n_level_blocks, kLevelBlock, k_level_count, T, b.tile_lvl,
            b.level_counts, b.n_level_blocks, K);
     LAUNCH(K_LEVEL_SCAN, 1, 1024, k_level_scan, b.level_counts, b.n_level_blocks, K, b.tile_ge,

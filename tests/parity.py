@@ -89,3 +89,29 @@ def ulp_sensitivity(sc, trials=3, seed=0):
         dx = max(dx, float(np.abs(x2 - x1).max()))
         dl = max(dl, float(np.abs(lam2 - lam1).max()))
     return dx, dl
+
+
+def adjoint_spread(sc, steps, cot_fn, trials=2, seed=0):
+    """Largest relative change of the oracle's reverse mode (max-norm, x and
+    v adjoints) when every input position moves by one float32 ulp (random
+    direction), with the same frozen structure.  cot_fn(x_T) gives the
+    output adjoints.  Rollouts through wall contacts are ill-conditioned:
+    a particle resting on a wall flips its clamp mask under such a change,
+    so multi-step tests take 4x this spread as their tolerance."""
+    import oracle
+
+    x0, v0 = sc.x0.astype(np.float64), sc.v0.astype(np.float64)
+    xT, _, frozen = oracle.rollout_structure(sc, x0, v0, steps)
+    rx, rv = oracle.rollout_vjp(sc, x0, v0, frozen, *cot_fn(xT))
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(trials):
+        x32 = x0.astype(np.float32)
+        up = np.nextafter(x32, np.float32(np.inf))
+        dn = np.nextafter(x32, np.float32(-np.inf))
+        xp = np.where(rng.integers(0, 2, size=x0.shape).astype(bool), up, dn).astype(np.float64)
+        xTp, _ = oracle.rollout_fixed(sc, xp, v0, frozen)
+        px, pv = oracle.rollout_vjp(sc, xp, v0, frozen, *cot_fn(xTp))
+        worst = max(worst, np.abs(px - rx).max() / np.abs(rx).max(),
+                    np.abs(pv - rv).max() / np.abs(rv).max())
+    return (xT, frozen, rx, rv), worst

@@ -215,6 +215,25 @@ def test_two_runs_bit_identical():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("extra", [0, 1, 3])
+def test_capacity_not_a_multiple_of_eight(extra):
+    # neighbour lists are stored in groups of eight codes; a capacity that is
+    # not a multiple of eight must still hold every list that fits it
+    sc = scenes.block(12, 10, 9, seed=14, n_min=2, n_max=6, levels="random", vel_sigma=0.3)
+    ref, most = [], 0
+    with _sim(sc) as a:
+        for _ in range(3):
+            a.step(1)
+            most = max(most, a.stats()["max_neighbours"])
+            ref.append((a.positions(), a.velocities()))
+    cap = most + extra
+    cap += 1 if cap % 8 == 0 else 0
+    with _sim(sc, max_neighbours=cap) as b:
+        for x, v in ref:
+            b.step(1)
+            assert np.array_equal(b.positions(), x) and np.array_equal(b.velocities(), v)
+
+
 def test_resume_from_saved_state_bit_identical():
     sc = scenes.block(12, 12, 12, seed=13, n_min=2, n_max=6, levels="random", vel_sigma=0.3)
     with _sim(sc) as a:
