@@ -43,6 +43,34 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3  # published vector FP32 peak (counts dual-issue)
 
 
+TRAFFIC_FILE = ROOT / "profiles" / "tank_1m_traffic.json"
+
+
+def kernel_sources_digest() -> str:
+    """SHA-1 over the forward-step kernel sources: the key under which
+    hardware-counter traffic figures are stored."""
+    import hashlib
+    h = hashlib.sha1()
+    csrc = ROOT / "paper_1608_04721_amd" / "csrc"
+    for name in ("pbf_internal.h", "pbf_kernels.hip"):
+        h.update(name.encode())
+        h.update((csrc / name).read_bytes())
+    return h.hexdigest()
+
+
+def _traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy), or None when
+    the kernel sources have changed since they were taken."""
+    try:
+        rec = json.loads(TRAFFIC_FILE.read_text())
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha1") != kernel_sources_digest():
+        return None
+    return rec.get("bytes_per_dispatch", {}).get(kernel)
+
+
 def _timed_run(sim, steps, warmup, stream, torch):
     sim.set_graph(True)
     sim.step(warmup)
@@ -115,7 +143,7 @@ def _roofline(prof, pairs, active):
                  "algorithmic_bytes_per_launch": int(bytes_),
                  "algorithmic_flop_per_launch": int(flops),
                  "hbm_model_gbs": round(gbs, 1), "alu_tflops": round(tflops, 3),
-                 "traffic": None})
+                 "traffic": _traffic(dom)})
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
                for k, v in prof.items() if v[1]}

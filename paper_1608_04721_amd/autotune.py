@@ -96,6 +96,7 @@ def tune(sim, steps: int = 3, use_cache: bool = True, verbose: bool = False) -> 
                 sim.set_block_size(k, t)
         return best
     best = {}
+    _time_kernels(sim, 1)  # first-touch and cold-cache costs stay out of the timings
     for kname, cands in CANDIDATES.items():
         timings = {}
         for t in cands:

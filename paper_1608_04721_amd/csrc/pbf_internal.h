@@ -20,11 +20,16 @@ constexpr int kTileThreads = 512;  // threads of a solver-pass tile workgroup (a
 constexpr int kNbrThreads = 256;   // threads of a neighbour-build tile workgroup (at most)
 constexpr int kBndWords = kStageRows * (kStageEdge + 1);  // cell bounds of the staged rows
 constexpr int kRowWords = kBndWords + kStageRows + 1;     // saved tables per tile
+constexpr uint32_t kXcds = 8;       // accelerator complex dies of an MI355X (own L2 each)
 constexpr int kSegOffBits = 10;    // fallback neighbour code: row << 10 | offset
 // LDS stage entry kStageCap (one past the staged particles) holds a point
 // this far away; its code pads the last group of a neighbour list
 constexpr uint32_t kFarCode = kStageCap;
 constexpr float kFar = 1e18f;
+// LDS stage array: the staged particles, the far entry, and spare entries so
+// that the neighbour scan may read up to three entries past any window
+constexpr int kStageSlack = 3;
+constexpr int kStageEntries = kStageCap + 1 + kStageSlack;
 // pmeta bit fields: level << 16 | neighbour count
 constexpr int kMetaLevel = 16;
 constexpr uint32_t kMetaCount = 0xffffu;

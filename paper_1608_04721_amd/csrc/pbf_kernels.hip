@@ -329,6 +329,19 @@ __device__ __forceinline__ TileLoc tile_locate(uint32_t tile, const uint32_t *__
     return t;
 }
 
+// The entry of tile_order that workgroup b handles when the first `active`
+// entries are listed.  Workgroups are dealt to the XCDs round robin (b %
+// kXcds), so each XCD is given one contiguous run of the list: tiles next to
+// each other, whose LDS stages share halo cells, then meet in the same L2.
+// False for workgroups past the list (the grid is rounded up to kXcds).
+__device__ __forceinline__ bool xcd_slot(uint32_t b, uint32_t active, uint32_t &slot)
+{
+    const uint32_t per = (active + kXcds - 1) / kXcds;
+    const uint32_t j = b / kXcds;
+    slot = (b % kXcds) * per + j;
+    return j < per && slot < active;
+}
+
 // Slot where staged cell x (0..kStageEdge; kStageEdge = end) of staged row
 // (sy, sz) begins.  Staged cells run from one cell before the tile to one
 // after it; cells left or right of the grid are empty ranges, and rows above,
@@ -574,18 +587,19 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                 uint32_t m = 0;
                 for (uint32_t c = 0; c < cl; c += 4) {
                     float4 xj[4];
+                    // past the window's end: other stage entries (the stage has
+                    // kStageSlack spare entries past the far entry), masked below
+                    const float4 *sp = stage + (l0 + c0 + c);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        // past the window's end: another staged particle or the
-                        // far entry, masked below; never past the stage
-                        xj[u] = FITS ? stage[min(l0 + c0 + c + u, kFarCode)]
-                                     : xs[min((int64_t)(ja + c0 + c + u), n - 1)];
-                    }
+                    for (int u = 0; u < 4; ++u)
+                        xj[u] = FITS ? sp[u] : xs[min((int64_t)(ja + c0 + c + u), n - 1)];
+                    uint32_t nib = 0;  // hits of the four, bit u
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
-                        m |= (dx * dx + dy * dy + dz * dz < h2) ? (1u << (c + u)) : 0u;
+                        nib |= (dx * dx + dy * dy + dz * dz < h2) ? (1u << u) : 0u;
                     }
+                    m |= nib << c;
                 }
                 if (cl < 32u) m &= (1u << cl) - 1u;
                 if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1u << (i - ja - c0));  // not itself
@@ -632,9 +646,10 @@ __global__ __launch_bounds__(kNbrThreads) void k_neighbours(
     uint32_t *__restrict__ rows, uint32_t *__restrict__ err)
 {
     __shared__ TileTables tb;
-    __shared__ float4 stage[kStageCap + 1];
-    if (blockIdx.x >= tile_ge[1]) return;  // empty tiles are not listed before this bound
-    const uint32_t tile = tile_order[blockIdx.x];
+    __shared__ float4 stage[kStageEntries];
+    uint32_t slot;
+    if (!xcd_slot(blockIdx.x, tile_ge[1], slot)) return;  // empty tiles are listed last
+    const uint32_t tile = tile_order[slot];
     const TileLoc t = tile_locate(tile, tile_scene, sc);
     const bool fits = tile_tables(t, cell_start, tb);
     // keep the tables for the solver passes of this step
@@ -770,9 +785,10 @@ __global__ __launch_bounds__(kTileThreads) void k_lambda(
     const uint32_t *__restrict__ pslot)
 {
     __shared__ TileTables tb;
-    __shared__ float4 stage[kStageCap + 1];
-    if (blockIdx.x >= tile_ge[k + 1]) return;
-    const uint32_t tile = tile_order[blockIdx.x];
+    __shared__ float4 stage[kStageEntries];
+    uint32_t slot;
+    if (!xcd_slot(blockIdx.x, tile_ge[k + 1], slot)) return;  // tiles with an active particle
+    const uint32_t tile = tile_order[slot];
     const SceneDev &S = sc[tile_scene[tile]];
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
     if (stage_rows(rows, tile, xs, tb, stage))
@@ -838,9 +854,10 @@ __global__ __launch_bounds__(kTileThreads) void k_update(
     const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot)
 {
     __shared__ TileTables tb;
-    __shared__ float4 stage[kStageCap + 1];
-    if (blockIdx.x >= tile_ge[k > 1 ? k : 1]) return;  // tiles with a particle of level >= k
-    const uint32_t tile = tile_order[blockIdx.x];
+    __shared__ float4 stage[kStageEntries];
+    uint32_t slot;  // tiles with a particle of level >= k
+    if (!xcd_slot(blockIdx.x, tile_ge[k > 1 ? k : 1], slot)) return;
+    const uint32_t tile = tile_order[slot];
     const SceneDev &S = sc[tile_scene[tile]];
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
     if (stage_rows(rows, tile, xs_in, tb, stage))
@@ -927,6 +944,7 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     const int nxt = cur ^ 1;
     const int K = b.n_iters;
     const uint32_t G = b.n_cells, T = b.n_tiles;
+    const uint32_t TX = (T + kXcds - 1) / kXcds * kXcds;  // tile grids, see xcd_slot
     const int *bs = ls.block;
     hipError_t e;
 
@@ -954,18 +972,18 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
            b.level_part, blocks_for(n, bs[K_LOD_PREDICT]), b.totals);
     LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
            b.level_counts, b.n_level_blocks, K, b.tile_order);
-    LAUNCH(K_NEIGHBOURS, T, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
+    LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
            b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap, b.nbr,
            b.pmeta, b.pslot, b.tile_rows, b.err);
     for (int k = 0; k < K; ++k) {
         float4 *xin = b.xs[k & 1], *xout = b.xs[(k + 1) & 1];
-        LAUNCH(K_LAMBDA, T, bs[K_LAMBDA], k_lambda, k, b.scenes, b.tile_scene, b.tile_order,
+        LAUNCH(K_LAMBDA, TX, bs[K_LAMBDA], k_lambda, k, b.scenes, b.tile_scene, b.tile_order,
                b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr, b.pmeta,
                b.pslot);
         if (rec && (e = hipMemcpyAsync(rec->snap[k], xin, sizeof(float4) * n,
                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;
-        LAUNCH(K_UPDATE, T, bs[K_UPDATE], k_update, k, b.scenes, b.tile_scene, b.tile_order,
+        LAUNCH(K_UPDATE, TX, bs[K_UPDATE], k_update, k, b.scenes, b.tile_scene, b.tile_order,
                b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, xout, n, b.nbr, b.pmeta,
                b.pslot);
     }
