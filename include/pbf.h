@@ -222,7 +222,11 @@ pbf_status pbf_rollout_forward(pbf_ctx *ctx, int32_t n_steps, int32_t ckpt_every
  * Eqs. 4-7 and of Fig. 7's prediction and update); every segment between
  * checkpoints is recomputed from its checkpoint.  All four buffers are host
  * memory (on_device = 0, synchronises) or device memory (1).  The context
- * is left at the final state of the rollout, stored in ID order. */
+ * is left at the final state of the rollout, stored in ID order (after an
+ * error its state is unspecified).  The checkpoints and the reverse pass's
+ * work buffers (per recorded step: n (K+1) 16 B of positions plus the
+ * neighbour codes) stay allocated in the context for the next call of the
+ * same shape, until pbf_destroy. */
 pbf_status pbf_rollout_backward(pbf_ctx *ctx, const float *dl_dx, const float *dl_dv,
                                 float *dl_dx0, float *dl_dv0, int32_t on_device);
 

@@ -96,6 +96,15 @@ struct pbf_ctx {
     std::vector<float *> ckpt;  // x0, v0, x1, v1, ... (pairs)
     int32_t roll_steps = 0, roll_every = 0;
     bool roll_valid = false;
+    // work buffers of the reverse pass, kept for the next call of the same shape
+    struct {
+        std::vector<void *> bufs;
+        int32_t seg_len = 0;
+        float *ax = nullptr, *av = nullptr, *fx = nullptr, *fv = nullptr;
+        unsigned long long *tot = nullptr;
+        pbf::AdjointScratch w{};
+        std::vector<pbf::StepRecord> recs;
+    } rs;
 };
 
 namespace {
@@ -366,6 +375,7 @@ void pbf_destroy(pbf_ctx *c)
     }
     for (void *p : c->allocs) (void)hipFree(p);
     for (float *p : c->ckpt) (void)hipFree(p);
+    for (void *p : c->rs.bufs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -880,16 +890,18 @@ pbf_status pbf_rollout_forward(pbf_ctx *c, int32_t n_steps, int32_t ckpt_every)
     if (n_steps < 1 || ckpt_every < 1)
         return fail(c, PBF_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
-    for (float *p : c->ckpt) (void)hipFree(p);
-    c->ckpt.clear();
     c->roll_valid = false;
     const size_t n3 = (size_t)c->n_total * 3;
     const int32_t nck = (n_steps + ckpt_every - 1) / ckpt_every;
-    for (int32_t k = 0; k < 2 * nck; ++k) {
-        float *p = nullptr;
-        hipError_t e = hipMalloc((void **)&p, std::max<size_t>(n3, 1) * sizeof(float));
-        if (e != hipSuccess) return hip_fail(c, e, "checkpoint buffers");
-        c->ckpt.push_back(p);
+    if (c->ckpt.size() != (size_t)(2 * nck)) {  // kept from the last rollout if the count matches
+        for (float *p : c->ckpt) (void)hipFree(p);
+        c->ckpt.clear();
+        for (int32_t k = 0; k < 2 * nck; ++k) {
+            float *p = nullptr;
+            hipError_t e = hipMalloc((void **)&p, std::max<size_t>(n3, 1) * sizeof(float));
+            if (e != hipSuccess) return hip_fail(c, e, "checkpoint buffers");
+            c->ckpt.push_back(p);
+        }
     }
     for (int32_t s = 0; s < n_steps; ++s) {
         if (s % ckpt_every == 0) {
@@ -924,53 +936,63 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
     const int K = c->b.n_iters;
     const int32_t T = c->roll_steps, C = c->roll_every;
     const int32_t seg_len = std::min(C, T);
-    std::vector<void *> tmp;
-    auto alloc = [&](size_t bytes) -> void * {
-        void *p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 1)) != hipSuccess) return nullptr;
-        tmp.push_back(p);
-        return p;
-    };
-    auto release = [&]() {
-        for (void *p : tmp) (void)hipFree(p);
-        tmp.clear();
-    };
-    // adjoint state (ID order) and the final state to restore afterwards
-    float *ax = (float *)alloc(n3 * 4), *av = (float *)alloc(n3 * 4);
-    float *fx = (float *)alloc(n3 * 4), *fv = (float *)alloc(n3 * 4);
-    // the recomputed steps must not count in the context's running totals
-    unsigned long long *tot = (unsigned long long *)alloc(2 * sizeof(unsigned long long));
-    AdjointScratch w{};
-    w.nslot = (uint32_t *)alloc((size_t)n * c->b.nbr_cap * 4);
-    w.zb = (float4 *)alloc((size_t)n * 16);
-    w.xb = (float4 *)alloc((size_t)n * 16);
-    w.dpb = (float4 *)alloc((size_t)n * 16);
-    w.gc = (float4 *)alloc((size_t)n * 16);
-    w.lb = (float *)alloc((size_t)n * 4);
-    w.sb = (float *)alloc((size_t)n * 4);
-    std::vector<StepRecord> recs((size_t)seg_len);
-    const size_t T_t = c->b.n_tiles;
-    bool ok = ax && av && fx && fv && tot && w.nslot && w.zb && w.xb && w.dpb && w.gc && w.lb && w.sb;
-    for (auto &r : recs) {
-        if (!ok) break;
-        r.id = (uint32_t *)alloc((size_t)n * 4);
-        r.lvl = (uint8_t *)alloc((size_t)n);
-        r.nbr = (uint4 *)alloc((size_t)n * (c->b.nbr_stride / 8) * 16);
-        r.pmeta = (uint32_t *)alloc((size_t)n * 4);
-        r.pslot = (uint32_t *)alloc((size_t)n * 4);
-        r.tile_rows = (uint32_t *)alloc(T_t * kRowWords * 4);
-        r.tile_order = (uint32_t *)alloc(T_t * 4);
-        r.tile_start = (uint32_t *)alloc((T_t + 1) * 4);
-        r.tile_count = (uint32_t *)alloc(T_t * 4);
-        r.tile_ge = (uint32_t *)alloc((PBF_MAX_ITERS + 2) * 4);
-        ok = r.id && r.lvl && r.nbr && r.pmeta && r.pslot && r.tile_rows && r.tile_order &&
-             r.tile_start && r.tile_count && r.tile_ge;
-        for (int k = 0; k <= K && ok; ++k) ok = (r.snap[k] = (float4 *)alloc((size_t)n * 16)) != nullptr;
+    auto &rs = c->rs;
+    if (rs.seg_len != seg_len) {  // (re)allocate the work buffers for this segment length
+        for (void *p : rs.bufs) (void)hipFree(p);
+        rs.bufs.clear();
+        rs.seg_len = 0;
+        auto alloc = [&](size_t bytes) -> void * {
+            void *p = nullptr;
+            if (hipMalloc(&p, std::max<size_t>(bytes, 1)) != hipSuccess) return nullptr;
+            rs.bufs.push_back(p);
+            return p;
+        };
+        // adjoint state (ID order), the final state to restore afterwards, and
+        // the running totals (the recomputed steps must not count in them)
+        rs.ax = (float *)alloc(n3 * 4);
+        rs.av = (float *)alloc(n3 * 4);
+        rs.fx = (float *)alloc(n3 * 4);
+        rs.fv = (float *)alloc(n3 * 4);
+        rs.tot = (unsigned long long *)alloc(2 * sizeof(unsigned long long));
+        AdjointScratch &w = rs.w;
+        w.nslot = (uint32_t *)alloc((size_t)n * c->b.nbr_cap * 4);
+        w.zb = (float4 *)alloc((size_t)n * 16);
+        w.xb = (float4 *)alloc((size_t)n * 16);
+        w.dpb = (float4 *)alloc((size_t)n * 16);
+        w.gc = (float4 *)alloc((size_t)n * 16);
+        w.lb = (float *)alloc((size_t)n * 4);
+        w.sb = (float *)alloc((size_t)n * 4);
+        rs.recs.assign((size_t)seg_len, StepRecord{});
+        const size_t T_t = c->b.n_tiles;
+        bool ok = rs.ax && rs.av && rs.fx && rs.fv && rs.tot && w.nslot && w.zb && w.xb && w.dpb &&
+                  w.gc && w.lb && w.sb;
+        for (auto &r : rs.recs) {
+            if (!ok) break;
+            r.id = (uint32_t *)alloc((size_t)n * 4);
+            r.lvl = (uint8_t *)alloc((size_t)n);
+            r.nbr = (uint4 *)alloc((size_t)n * (c->b.nbr_stride / 8) * 16);
+            r.pmeta = (uint32_t *)alloc((size_t)n * 4);
+            r.pslot = (uint32_t *)alloc((size_t)n * 4);
+            r.tile_rows = (uint32_t *)alloc(T_t * kRowWords * 4);
+            r.tile_order = (uint32_t *)alloc(T_t * 4);
+            r.tile_start = (uint32_t *)alloc((T_t + 1) * 4);
+            r.tile_count = (uint32_t *)alloc(T_t * 4);
+            r.tile_ge = (uint32_t *)alloc((PBF_MAX_ITERS + 2) * 4);
+            ok = r.id && r.lvl && r.nbr && r.pmeta && r.pslot && r.tile_rows && r.tile_order &&
+                 r.tile_start && r.tile_count && r.tile_ge;
+            for (int k = 0; k <= K && ok; ++k) ok = (r.snap[k] = (float4 *)alloc((size_t)n * 16)) != nullptr;
+        }
+        if (!ok) {
+            for (void *p : rs.bufs) (void)hipFree(p);
+            rs.bufs.clear();
+            return fail(c, PBF_ERR_OUT_OF_MEMORY, "rollout backward buffers");
+        }
+        rs.seg_len = seg_len;
     }
-    if (!ok) {
-        release();
-        return fail(c, PBF_ERR_OUT_OF_MEMORY, "rollout backward buffers");
-    }
+    float *ax = rs.ax, *av = rs.av, *fx = rs.fx, *fv = rs.fv;
+    unsigned long long *tot = rs.tot;
+    const AdjointScratch &w = rs.w;
+    std::vector<StepRecord> &recs = rs.recs;
     hipError_t e = hipSuccess;
     const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -979,7 +1001,6 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
         if ((e = (X)) != hipSuccess) {                 \
             pbf_status r_ = hip_fail(c, e, WHAT);      \
             (void)hipStreamSynchronize(c->stream);     \
-            release();                                 \
             return r_;                                 \
         }                                              \
     } while (0)
@@ -1014,7 +1035,6 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
     c->stepped = false;
     BCHK(hipStreamSynchronize(c->stream), "stream synchronize");
 #undef BCHK
-    release();
     return latched(c);
 }
 
