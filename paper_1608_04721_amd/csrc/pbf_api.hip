@@ -229,7 +229,7 @@ void drop_graphs(pbf_ctx *c)
 bool fixed_shape(int k)
 {
     return k == K_SCAN_REDUCE || k == K_SCAN_TOP || k == K_SCAN_APPLY || k == K_LEVEL_COUNT ||
-           k == K_LEVEL_SCAN || k == K_LEVEL_SCATTER;
+           k == K_LEVEL_SCAN || k == K_LEVEL_SCATTER || k == K_TILE_TABLES;
 }
 
 // tile kernels are compiled for a bounded block size

@@ -15,7 +15,7 @@ constexpr int kTileEdge = 4;
 constexpr int kStageEdge = kTileEdge + 2;
 constexpr int kStageRows = kStageEdge * kStageEdge;
 constexpr int kOwnRows = kTileEdge * kTileEdge;
-constexpr int kStageCap = 3072;    // float4 entries staged in LDS (48 KiB)
+constexpr int kStageCap = 2304;    // float4 entries staged in LDS (36 KiB)
 constexpr int kTileThreads = 512;  // threads of a solver-pass tile workgroup (at most)
 constexpr int kNbrThreads = 256;   // threads of a neighbour-build tile workgroup (at most)
 constexpr int kBndWords = kStageRows * (kStageEdge + 1);  // cell bounds of the staged rows
@@ -73,6 +73,7 @@ enum Kernel : int {
     K_LEVEL_COUNT,
     K_LEVEL_SCAN,
     K_LEVEL_SCATTER,
+    K_TILE_TABLES,
     K_NEIGHBOURS,
     K_LAMBDA,
     K_UPDATE,
@@ -86,6 +87,7 @@ extern const int kDefaultBlock[K_COUNT];
 constexpr int kLevelBlock = 256;  // items per level-bucketing block (fixed: 4 waves)
 constexpr int kScanItems = 8;     // items per thread in the exclusive scans
 constexpr int kScanBlock = 256;   // threads of a scan block (2048 items)
+constexpr uint32_t kFusedTiles = 16384;  // up to this many tiles, one workgroup does the tile tables
 
 // Every buffer one step touches.  Storage ("slot") order is the cell order
 // of the last counting sort.  Per-particle solver data ("p" order) is laid

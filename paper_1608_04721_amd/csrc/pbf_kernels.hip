@@ -33,12 +33,12 @@ namespace pbf {
 const char *const kKernelNames[K_COUNT] = {
     "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
     "sort_finish",  "tile_prepare", "level_count", "level_scan",  "level_scatter",
-    "neighbours",   "lambda",      "update",       "commit"};
+    "tile_tables",  "neighbours",  "lambda",       "update",      "commit"};
 
 const int kDefaultBlock[K_COUNT] = {256,          kScanBlock,   1024,         kScanBlock,
                                     256,          256,          256,          kLevelBlock,
-                                    1024,         kLevelBlock,  kNbrThreads,  kTileThreads,
-                                    kTileThreads, 256};
+                                    1024,         kLevelBlock,  1024,         kNbrThreads,
+                                    kTileThreads, kTileThreads, 256};
 
 namespace {
 
@@ -521,6 +521,117 @@ __global__ void k_level_scatter(uint32_t m, const uint8_t *__restrict__ lvl,
     }
 }
 
+// One workgroup of 1024 threads for contexts with few tiles (T <=
+// kFusedTiles): the exclusive scan of the tile counts, the stable bucketing
+// of the tiles by descending level with the prefix counts ge[L] (tiles with
+// level >= L), and the running totals -- what k_scan_* and k_level_* do in
+// six launches.  The order is the same: descending level, ties by tile index.
+__global__ __launch_bounds__(1024) void k_tile_tables(
+    uint32_t T, int K, const uint32_t *__restrict__ tile_count, const uint8_t *__restrict__ tile_lvl,
+    uint32_t *__restrict__ tile_start, uint32_t *__restrict__ order, uint32_t *__restrict__ ge,
+    const uint32_t *__restrict__ level_part, uint32_t n_part,
+    unsigned long long *__restrict__ totals)
+{
+    __shared__ uint32_t lds[1024 / 64 + 1];
+    __shared__ uint32_t hist[PBF_MAX_ITERS + 2];   // tiles per level, then running bucket offsets
+    __shared__ uint32_t wc[1024 / 64][PBF_MAX_ITERS + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // exclusive scan of the tile counts, kScanItems consecutive tiles per thread
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x * kScanItems) {
+        const uint32_t base = b0 + threadIdx.x * (uint32_t)kScanItems;
+        uint32_t vals[kScanItems], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            vals[q] = base + q < T ? tile_count[base + q] : 0u;
+            sum += vals[q];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_exclusive_sum(sum, lds, &tot);
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            if (base + q < T) tile_start[base + q] = run;
+            run += vals[q];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) tile_start[T] = carry;
+    // level histogram (one LDS atomic per level present in a wave), then
+    // bucket starts in descending level order
+    for (int L = threadIdx.x; L <= K + 1; L += blockDim.x) hist[L] = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x) {
+        const uint32_t s = b0 + threadIdx.x;
+        const bool valid = s < T;
+        const int L = valid ? (int)tile_lvl[s] : 0;
+        uint64_t rem = __ballot(valid);
+        while (rem) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int L0 = __shfl(L, leader, 64);
+            const uint64_t mm = __ballot(valid && L == L0);
+            if (lane == leader) atomicAdd(&hist[L0], (uint32_t)__popcll(mm));
+            rem &= ~mm;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int L = K; L >= 0; --L) {
+            const uint32_t c = hist[L];
+            hist[L] = run;  // first position of level L
+            run += c;
+            ge[L] = run;    // tiles with level >= L
+        }
+        ge[K + 1] = 0;
+    }
+    __syncthreads();
+    // stable scatter, 1024 tiles per round: rank inside the wave by ballots,
+    // then across the waves of the round, then the bucket's running offset
+    for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x) {
+        for (int i = threadIdx.x; i < nw * (PBF_MAX_ITERS + 1); i += blockDim.x) (&wc[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t s = b0 + threadIdx.x;
+        const bool valid = s < T;
+        const int L = valid ? (int)tile_lvl[s] : 0;
+        uint64_t rem = __ballot(valid);
+        uint32_t rank = 0;
+        while (rem) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int L0 = __shfl(L, leader, 64);
+            const uint64_t mm = __ballot(valid && L == L0);
+            if (valid && L == L0) rank = (uint32_t)__popcll(mm & ((1ull << lane) - 1ull));
+            if (lane == leader) wc[wave][L0] = (uint32_t)__popcll(mm);
+            rem &= ~mm;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += wc[w][L];
+            order[hist[L] + before + rank] = s;
+        }
+        __syncthreads();
+        // advance the running offsets by this round's counts
+        for (int L2 = threadIdx.x; L2 <= K; L2 += blockDim.x) {
+            uint32_t c = 0;
+            for (int w = 0; w < nw; ++w) c += wc[w][L2];
+            hist[L2] += c;
+        }
+        __syncthreads();
+    }
+    // running count of particle-iterations (sum_i N_i) and of steps
+    uint32_t part = 0;
+    for (uint32_t e = threadIdx.x; e < n_part; e += blockDim.x) part += level_part[e];
+    part = wave_sum(part);
+    if (lane == 0) lds[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long pit = 0;
+        for (int w = 0; w < nw; ++w) pit += lds[w];
+        totals[0] += pit;
+        totals[1] += 1ull;
+    }
+}
+
 // ------------------------------------------------------ neighbour lists
 // N_i = { j != i : |x*_i - x*_j|^2 < h^2 } over the 27 cells around x*_i
 // (Fig. 7 second loop), kept for every iteration of the step.  The 27 cells
@@ -776,7 +887,7 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
 
 // lambda_i of the tile's active particles, written to xs[i].w; neighbours
 // read only xyz of the same buffer.
-__global__ __launch_bounds__(kTileThreads) void k_lambda(
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_lambda(
     int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
@@ -845,7 +956,7 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
 // (Jacobi).  Particles that finished with this iteration (N_i == k) copy
 // position and lambda across, so that both buffers hold their final values
 // from now on.
-__global__ __launch_bounds__(kTileThreads) void k_update(
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_update(
     int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
@@ -964,14 +1075,19 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     LAUNCH(K_TILE_PREPARE, blocks_for((int64_t)T * 64, bs[K_TILE_PREPARE]), bs[K_TILE_PREPARE],
            k_tile_prepare, T, b.scenes, b.tile_scene, b.cell_start, b.lvl[nxt], b.tile_count,
            b.tile_lvl);
-    if ((e = enqueue_scan(b.tile_count, T, b.scan_part, b.tile_start, false, s, tm)) != hipSuccess)
-        return e;
-    LAUNCH(K_LEVEL_COUNT, b.n_level_blocks, kLevelBlock, k_level_count, T, b.tile_lvl,
-           b.level_counts, b.n_level_blocks, K);
-    LAUNCH(K_LEVEL_SCAN, 1, 1024, k_level_scan, b.level_counts, b.n_level_blocks, K, b.tile_ge,
-           b.level_part, blocks_for(n, bs[K_LOD_PREDICT]), b.totals);
-    LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
-           b.level_counts, b.n_level_blocks, K, b.tile_order);
+    if (T <= kFusedTiles) {
+        LAUNCH(K_TILE_TABLES, 1, 1024, k_tile_tables, T, K, b.tile_count, b.tile_lvl, b.tile_start,
+               b.tile_order, b.tile_ge, b.level_part, blocks_for(n, bs[K_LOD_PREDICT]), b.totals);
+    } else {
+        if ((e = enqueue_scan(b.tile_count, T, b.scan_part, b.tile_start, false, s, tm)) != hipSuccess)
+            return e;
+        LAUNCH(K_LEVEL_COUNT, b.n_level_blocks, kLevelBlock, k_level_count, T, b.tile_lvl,
+               b.level_counts, b.n_level_blocks, K);
+        LAUNCH(K_LEVEL_SCAN, 1, 1024, k_level_scan, b.level_counts, b.n_level_blocks, K, b.tile_ge,
+               b.level_part, blocks_for(n, bs[K_LOD_PREDICT]), b.totals);
+        LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
+               b.level_counts, b.n_level_blocks, K, b.tile_order);
+    }
     LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
            b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap, b.nbr,
            b.pmeta, b.pslot, b.tile_rows, b.err);

@@ -234,6 +234,18 @@ def test_capacity_not_a_multiple_of_eight(extra):
             assert np.array_equal(b.positions(), x) and np.array_equal(b.velocities(), v)
 
 
+def test_many_tiles():
+    # a small block in a large box: more tiles than one workgroup books (the
+    # multi-launch tile scan and level bucketing)
+    sc = scenes.block(10, 8, 9, seed=15, n_min=1, n_max=5, levels="random", vel_sigma=0.3,
+                      box=(np.zeros(3), np.full(3, 12.0)), origin=(5.0, 0.0, 5.0))
+    assert np.prod([-(-int(d) // 4) for d in sc.dims]) > 16384
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    with _sim(sc) as sim:
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info)
+
+
 def test_resume_from_saved_state_bit_identical():
     sc = scenes.block(12, 12, 12, seed=13, n_min=2, n_max=6, levels="random", vel_sigma=0.3)
     with _sim(sc) as a:
