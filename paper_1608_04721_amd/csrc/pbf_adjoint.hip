@@ -59,7 +59,7 @@ __device__ __forceinline__ float3 hess(float f, float e, float3 d, float3 v)
 
 __device__ __forceinline__ uint32_t level_of(uint32_t meta)
 {
-    return meta >> kMetaLevel;
+    return meta_level(meta);
 }
 
 // Decode the step's neighbour codes into slots, slot[q * n + p] (one tile

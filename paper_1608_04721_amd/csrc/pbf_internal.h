@@ -30,9 +30,19 @@ constexpr float kFar = 1e18f;
 // that the neighbour scan may read up to three entries past any window
 constexpr int kStageSlack = 3;
 constexpr int kStageEntries = kStageCap + 1 + kStageSlack;
-// pmeta bit fields: level << 16 | neighbour count
-constexpr int kMetaLevel = 16;
-constexpr uint32_t kMetaCount = 0xffffu;
+// pmeta bit fields: neighbour count (13 bits), level (6 bits), and the
+// particle's own index in its tile's LDS stage (13 bits; 0 when the stage
+// does not fit)
+constexpr uint32_t kMetaCountBits = 13;
+constexpr uint32_t kMetaCount = (1u << kMetaCountBits) - 1u;
+constexpr uint32_t kMetaLevelShift = kMetaCountBits;
+constexpr uint32_t kMetaSelfShift = kMetaCountBits + 6;
+__host__ __device__ inline uint32_t meta_level(uint32_t m) { return (m >> kMetaLevelShift) & 63u; }
+__host__ __device__ inline uint32_t meta_self(uint32_t m) { return m >> kMetaSelfShift; }
+__host__ __device__ inline uint32_t make_meta(uint32_t count, uint32_t level, uint32_t self)
+{
+    return count | (level << kMetaLevelShift) | (self << kMetaSelfShift);
+}
 
 // Per-scene constants on the device.  Derived on the host in double and
 // rounded once to float.

@@ -743,7 +743,7 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
             cnt = keep;
         }
         pslot[p] = i;
-        pmeta[p] = ((uint32_t)lvl[i] << kMetaLevel) | cnt;
+        pmeta[p] = make_meta(cnt, lvl[i], FITS ? tb.base[r] + (i - tb.bnd[r][0]) : 0u);
     }
     return bad;
 }
@@ -861,9 +861,9 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
     for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t meta = pmeta[p];
-        if ((int)(meta >> kMetaLevel) <= k) continue;
-        const uint32_t i = pslot[p];
-        const float4 xi = xs[i];
+        const uint32_t i = pslot[p];  // independent loads, issued together
+        if ((int)meta_level(meta) <= k) continue;
+        const float4 xi = FITS ? stage[meta_self(meta)] : xs[i];
         float sum6 = h6;  // the particle itself: (h^2 - 0)^3
         float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
         for_each_neighbour<FITS>(tb, stage, xs, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
@@ -926,10 +926,10 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
     for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t meta = pmeta[p];
-        const int L = (int)(meta >> kMetaLevel);
+        const uint32_t i = pslot[p];  // independent loads, issued together
+        const int L = (int)meta_level(meta);
         if (L < k) continue;
-        const uint32_t i = pslot[p];
-        const float4 xi = xs_in[i];
+        const float4 xi = FITS ? stage[meta_self(meta)] : xs_in[i];
         if (L == k) {
             xs_out[i] = xi;
             continue;
