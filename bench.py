@@ -90,10 +90,12 @@ def _timed_run(sim, steps, warmup, stream, torch):
     sim.sync()
     st = sim.stats()
     pit = st["total_particle_iterations"] - pit0
+    mean_rho, max_rho = sim.density()  # after the timed region
     return {"ms_per_step": total_ms / steps, "ms_median": float(np.median(per)),
             "wall_s": wall, "particle_iterations": int(pit),
             "value": pit / (total_ms * 1e-3), "mean_levels": pit / (steps * sim.n),
-            "max_neighbours": st["max_neighbours"]}
+            "max_neighbours": st["max_neighbours"],
+            "density": {"mean_rho_over_rho0": round(mean_rho, 6), "max_rho_over_rho0": round(max_rho, 6)}}
 
 
 def _profile(sc, steps, Sim, stream):
@@ -415,12 +417,16 @@ def main(argv=None):
         "kernels": kernels,
     }
     line["max_neighbours"] = apbf["max_neighbours"]
+    # the paper's quality measure: average density over all particles after
+    # warm-up + timed steps (APBF and PBF(10) from the same initial state)
+    line["density"] = {"apbf": apbf["density"]}
     if out_pbf:
         line["pbf"] = {str(N): ({"error": r["error"]} if "error" in r else
                                 {"ms_per_step": round(r["ms_per_step"], 4),
                                  "ms_median": round(r["ms_median"], 4),
                                  "value": round(r["value"], 1),
-                                 "max_neighbours": r["max_neighbours"]})
+                                 "max_neighbours": r["max_neighbours"],
+                                 "density": r["density"]})
                        for N, r in out_pbf.items()}
         for N in (10, 5):
             if "error" not in out_pbf[N]:

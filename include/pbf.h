@@ -207,6 +207,23 @@ pbf_status pbf_debug_levels(pbf_ctx *ctx, uint8_t *levels);
 pbf_status pbf_get_state(pbf_ctx *ctx, float *x, float *v, int64_t *step);
 pbf_status pbf_set_state(pbf_ctx *ctx, const float *x, const float *v, int64_t step);
 
+/* ---------------- quality measure ---------------- */
+
+/* Average density, the quality measure of the paper's evaluation (Section 7,
+ * Fig. 9): rho_i / rho0 (Eqs. 5-6 with the poly6 kernel, the particle itself
+ * included) of every particle of every scene at the positions after the
+ * last step, over neighbour sets found afresh at those positions (a counting
+ * sort and grid search of their own; the state, the last step's debug views
+ * and the running totals are unchanged).  out (host, double[2]): out[0] =
+ * mean over all particles, out[1] = maximum.  rho_rel (optional, NULL to
+ * skip): float[n_total] in ID order, host memory (on_device = 0) or device
+ * memory (1).  Synchronises.  PBF_ERR_INVALID_ARG if no step has run since
+ * the context was created or its state set; PBF_ERR_CAPACITY if the fresh
+ * search overflows the neighbour or staging capacity.  Its buffers (about
+ * the size of one step's neighbour structure) are allocated by the first
+ * call and kept until pbf_destroy. */
+pbf_status pbf_density(pbf_ctx *ctx, double *out, float *rho_rel, int32_t on_device);
+
 /* ---------------- differentiable rollout (training form) ---------------- */
 
 /* Advance every scene by n_steps >= 1 steps like pbf_step, keeping a device

@@ -271,6 +271,17 @@ class Sim:
         self._check(self._lib.pbf_set_state(self._ctx, x.ctypes.data, v.ctypes.data, int(step)),
                     "pbf_set_state")
 
+    def density(self, per_particle: bool = False):
+        """Average density after the last step: (mean, max) of rho_i / rho0
+        over all particles, plus the per-particle values in ID order if
+        per_particle."""
+        out = (ctypes.c_double * 2)()
+        rho = np.empty(self.n, np.float32) if per_particle else None
+        self._check(self._lib.pbf_density(self._ctx, out,
+                                          rho.ctypes.data if per_particle else None, 0),
+                    "pbf_density")
+        return (out[0], out[1], rho) if per_particle else (out[0], out[1])
+
     # ------------------------------------------------ differentiable rollout
     def rollout_forward(self, n_steps: int, ckpt_every: int = 1):
         """Advance n_steps steps, checkpointing every ckpt_every steps for a

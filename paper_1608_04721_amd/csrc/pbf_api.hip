@@ -96,6 +96,9 @@ struct pbf_ctx {
     std::vector<float *> ckpt;  // x0, v0, x1, v1, ... (pairs)
     int32_t roll_steps = 0, roll_every = 0;
     bool roll_valid = false;
+    // average-density buffers (allocated by the first pbf_density)
+    pbf::DensityBuffers dens{};
+    float *dens_rho_id = nullptr;
     // work buffers of the reverse pass, kept for the next call of the same shape
     struct {
         std::vector<void *> bufs;
@@ -839,6 +842,63 @@ pbf_status pbf_debug_lambda(pbf_ctx *c, float *lambda)
     if ((st = d2h(c, id, c->b.id[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
     for (size_t s = 0; s < id.size(); ++s) lambda[id[s]] = xs[s].w;
     return PBF_OK;
+}
+
+pbf_status pbf_density(pbf_ctx *c, double *out, float *rho_rel, int32_t on_device)
+{
+    if (!c || !out) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    const int64_t n = c->n_total;
+    if (n == 0) {
+        out[0] = out[1] = 0.0;
+        return PBF_OK;
+    }
+    DensityBuffers &d = c->dens;
+    if (!d.out) {
+        const size_t T = c->b.n_tiles, parts = (T + kXcds - 1) / kXcds * kXcds;
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = dalloc(c, &d.xs, (size_t)n);
+        if (e == hipSuccess) e = dalloc(c, &d.key, (size_t)n);
+        if (e == hipSuccess) e = dalloc(c, &d.nbr, (size_t)n * (size_t)(c->b.nbr_stride / 8));
+        if (e == hipSuccess) e = dalloc(c, &d.pmeta, (size_t)n);
+        if (e == hipSuccess) e = dalloc(c, &d.pslot, (size_t)n);
+        if (e == hipSuccess) e = dalloc(c, &d.tile_rows, T * kRowWords);
+        if (e == hipSuccess) e = dalloc(c, &d.tile_order, T);
+        if (e == hipSuccess) e = dalloc(c, &d.tile_start, T + 1);
+        if (e == hipSuccess) e = dalloc(c, &d.tile_count, T);
+        if (e == hipSuccess) e = dalloc(c, &d.tile_ge, (size_t)PBF_MAX_ITERS + 2);
+        if (e == hipSuccess) e = dalloc(c, &d.tile_lvl, T);
+        if (e == hipSuccess) e = dalloc(c, &d.err, 1);
+        if (e == hipSuccess) e = dalloc(c, &d.totals, 2);
+        if (e == hipSuccess) e = dalloc(c, &d.rho_slot, (size_t)n);
+        if (e == hipSuccess) e = dalloc(c, &d.part_sum, parts);
+        if (e == hipSuccess) e = dalloc(c, &d.part_max, parts);
+        if (e == hipSuccess) e = dalloc(c, &c->dens_rho_id, (size_t)n);
+        if (e == hipSuccess) e = dalloc(c, &d.out, 2);
+        if (e != hipSuccess) {
+            d.out = nullptr;  // allocated parts are freed by pbf_destroy; retried next call
+            return hip_fail(c, e, "density buffers");
+        }
+    }
+    float *rho_id = rho_rel ? (on_device ? rho_rel : c->dens_rho_id) : nullptr;
+    HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), c->stream), "clear faults");
+    HIPCHK(c, enqueue_density(c->b, c->cur, c->ls, d, rho_id, c->stream), "density");
+    uint32_t bad = 0;
+    HIPCHK(c, hipMemcpyAsync(out, d.out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+           "density out");
+    HIPCHK(c, hipMemcpyAsync(&bad, d.err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
+           "density faults");
+    if (rho_rel && !on_device)
+        HIPCHK(c, hipMemcpyAsync(rho_rel, rho_id, (size_t)n * sizeof(float), hipMemcpyDeviceToHost,
+                                 c->stream),
+               "density out");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (bad & ERR_NEIGHBOUR_CAP)
+        return fail(c, PBF_ERR_CAPACITY, "pbf_density: a particle exceeded the neighbour capacity");
+    if (bad & ERR_CELL_CAP)
+        return fail(c, PBF_ERR_CAPACITY, "pbf_density: a cell or staged row exceeded its capacity");
+    return latched(c);
 }
 
 pbf_status pbf_debug_levels(pbf_ctx *c, uint8_t *levels)

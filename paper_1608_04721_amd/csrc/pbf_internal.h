@@ -187,6 +187,30 @@ hipError_t enqueue_load_state(int64_t n, const float *x3, const float *v3,
                               const uint32_t *id_scene, float4 *x, float4 *v, uint32_t *id,
                               hipStream_t s);
 
+// Buffers of the average-density measure: a fresh neighbour structure of the
+// current positions (sizes as in StepBuffers), its own fault word and
+// totals, and the results.
+struct DensityBuffers {
+    float4 *xs;              // current positions in the fresh cell order
+    uint32_t *key;
+    uint4 *nbr;
+    uint32_t *pmeta, *pslot;
+    uint32_t *tile_rows, *tile_order, *tile_start, *tile_count, *tile_ge;
+    uint8_t *tile_lvl;
+    uint32_t *err;
+    unsigned long long *totals;
+    float *rho_slot;         // rho_i / rho0 per fresh slot
+    double *part_sum;        // per tile workgroup (n_tiles rounded up to kXcds)
+    float *part_max;
+    double *out;             // [0] mean, [1] max
+};
+
+// rho_i / rho0 of every particle at the positions of half `cur` (Eqs. 5-6)
+// over neighbour sets found afresh at those positions; half cur ^ 1 is used
+// as scratch.  rho_id (if not null): float[n] in ID order.
+hipError_t enqueue_density(const StepBuffers &b, int cur, const LaunchShape &ls,
+                           const DensityBuffers &d, float *rho_id, hipStream_t s);
+
 // Scatter slot-ordered positions (or velocities) into ID order for the IDs
 // [id_lo, id_hi): out[3 (id - id_lo) + c].
 hipError_t enqueue_unpermute(int64_t n, const float4 *x, const uint32_t *id, float *out,

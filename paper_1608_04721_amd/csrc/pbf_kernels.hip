@@ -115,6 +115,29 @@ __device__ __forceinline__ int dtc_level(float x, float y, float z, float cx, fl
     return min(max(L, nmin), nmax);
 }
 
+// Ticket of a particle inside its cell from the counting-sort histogram (all
+// lanes of the wave call; valid lanes form a prefix of the wave).  Runs of
+// lanes with equal keys (consecutive slots usually share a cell) take their
+// tickets with one atomic issued by the run's first lane; all run heads of
+// the wave issue together.
+__device__ __forceinline__ uint32_t cell_ticket(uint32_t k, bool valid, uint32_t *__restrict__ cell_count)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t kprev = __shfl_up(k, 1, 64);
+    const bool head = valid && (lane == 0 || kprev != k);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = heads & ((2ull << lane) - 1ull);              // heads at or below lane
+    const int my_head = 63 - __clzll((long long)upto);                  // valid lanes have one
+    const uint64_t above = heads & ~((2ull << lane) - 1ull);
+    const uint64_t valid_mask = __ballot(valid);
+    const int run_end = above ? (__ffsll((unsigned long long)above) - 1)
+                              : (64 - __clzll((long long)valid_mask));  // one past the last valid lane
+    uint32_t base = 0;
+    if (head) base = atomicAdd(&cell_count[k], (uint32_t)(run_end - lane));
+    base = __shfl(base, valid ? my_head : lane, 64);
+    return base + (uint32_t)(lane - my_head);
+}
+
 // --------------------------------------------- levels + forces + prediction
 // Fig. 7 first loop for every particle, plus the level N_i (Eq. 8, adaption
 // model of Section 4.1) from the position at the start of the step, the cell
@@ -164,22 +187,8 @@ __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
         k = S.cell_off + (uint32_t)(((int64_t)cz * S.dims[1] + cy) * S.dims[0] + cx);
         key[s] = k;
     }
-    // Runs of lanes with equal keys (consecutive slots usually share a cell)
-    // take their tickets with one atomic issued by the run's first lane; all
-    // run heads of the wave issue together.
-    const uint32_t kprev = __shfl_up(k, 1, 64);
-    const bool head = valid && (lane == 0 || kprev != k);
-    const uint64_t heads = __ballot(head);
-    const uint64_t upto = heads & ((2ull << lane) - 1ull);              // heads at or below lane
-    const int my_head = 63 - __clzll((long long)upto);                  // valid lanes have one
-    const uint64_t above = heads & ~((2ull << lane) - 1ull);
-    const uint64_t valid_mask = __ballot(valid);
-    const int run_end = above ? (__ffsll((unsigned long long)above) - 1)
-                              : (64 - __clzll((long long)valid_mask));  // one past the last valid lane
-    uint32_t base = 0;
-    if (head) base = atomicAdd(&cell_count[k], (uint32_t)(run_end - lane));
-    base = __shfl(base, valid ? my_head : lane, 64);
-    if (valid) ticket[s] = base + (uint32_t)(lane - my_head);
+    const uint32_t tk = cell_ticket(k, valid, cell_count);
+    if (valid) ticket[s] = tk;
     // sum of N_i over the block, for the running particle-iteration count
     const uint32_t lsum = wave_sum((uint32_t)L);
     if (lane == 0) wsum[threadIdx.x >> 6] = lsum;
@@ -977,6 +986,158 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
         tile_update<false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown);
 }
 
+// ------------------------------------------------ average density
+// Cell keys and histogram tickets of the current positions (no prediction):
+// the start of a fresh neighbour search for the density measure.
+__global__ void k_density_keys(int64_t n, const SceneDev *__restrict__ sc,
+                               const float4 *__restrict__ x, float4 *__restrict__ xs,
+                               uint32_t *__restrict__ key, uint32_t *__restrict__ ticket,
+                               uint32_t *__restrict__ cell_count)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = s < n;
+    uint32_t k = 0xffffffffu;
+    if (valid) {
+        const float4 xi = x[s];
+        const SceneDev &S = sc[__float_as_int(xi.w)];
+        const int cx = cell_coord(xi.x, S.lo[0], S.h, S.dims[0]);
+        const int cy = cell_coord(xi.y, S.lo[1], S.h, S.dims[1]);
+        const int cz = cell_coord(xi.z, S.lo[2], S.h, S.dims[2]);
+        k = S.cell_off + (uint32_t)(((int64_t)cz * S.dims[1] + cy) * S.dims[0] + cx);
+        xs[s] = make_float4(xi.x, xi.y, xi.z, 0.f);
+        key[s] = k;
+    }
+    const uint32_t tk = cell_ticket(k, valid, cell_count);
+    if (valid) ticket[s] = tk;
+}
+
+// rho_i / rho0 (Eqs. 5-6, the particle itself included) of every particle at
+// the positions after the last step, over that step's neighbour sets; the
+// quality measure of the paper's evaluation is the average over all
+// particles.  Per workgroup: the sum (double, reduced in a fixed order) and
+// the maximum; k_density_finish adds the workgroups up, again in a fixed
+// order, so the result is deterministic.
+template <bool FITS>
+__device__ __forceinline__ void tile_density(const SceneDev &S, const TileTables &tb,
+                                             const float4 *__restrict__ stage,
+                                             const float4 *__restrict__ x, int64_t n,
+                                             const uint4 *__restrict__ nbr,
+                                             const uint32_t *__restrict__ pmeta,
+                                             const uint32_t *__restrict__ pslot, uint32_t p0,
+                                             uint32_t nown, float *__restrict__ rho, double &sum,
+                                             float &mx)
+{
+    const float h2 = S.h2, h6 = S.h6, crho = S.c_rho;
+    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+        const size_t p = p0 + pl;
+        const uint32_t meta = pmeta[p];
+        const uint32_t i = pslot[p];
+        const float4 xi = FITS ? stage[meta_self(meta)] : x[i];
+        float sum6 = h6;
+        for_each_neighbour<FITS>(tb, stage, x, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float w = fmaxf(h2 - (dx * dx + dy * dy + dz * dz), 0.f);
+            sum6 += w * w * w;
+        });
+        const float r = crho * sum6;
+        rho[i] = r;
+        sum += (double)r;
+        mx = fmaxf(mx, r);
+    }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_density(
+    const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
+    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
+    const uint32_t *__restrict__ rows, const float4 *__restrict__ x, int64_t n,
+    const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
+    const uint32_t *__restrict__ pslot, float *__restrict__ rho, double *__restrict__ part_sum,
+    float *__restrict__ part_max)
+{
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageEntries];
+    __shared__ double dsum[kTileThreads / 64];
+    __shared__ float dmax[kTileThreads / 64];
+    double sum = 0.0;
+    float mx = 0.f;
+    uint32_t slot;
+    if (xcd_slot(blockIdx.x, tile_ge[1], slot)) {  // uniform per workgroup
+        const uint32_t tile = tile_order[slot];
+        const SceneDev &S = sc[tile_scene[tile]];
+        const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+        if (stage_rows(rows, tile, x, tb, stage))
+            tile_density<true>(S, tb, stage, x, n, nbr, pmeta, pslot, p0, nown, rho, sum, mx);
+        else
+            tile_density<false>(S, tb, stage, x, n, nbr, pmeta, pslot, p0, nown, rho, sum, mx);
+    }
+    // fixed-order reduction: lanes by a butterfly, then waves in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 64);
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        dsum[threadIdx.x >> 6] = sum;
+        dmax[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        float m = 0.f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            s += dsum[w];
+            m = fmaxf(m, dmax[w]);
+        }
+        part_sum[blockIdx.x] = s;
+        part_max[blockIdx.x] = m;
+    }
+}
+
+// one workgroup: out[0] = sum of the parts / n, out[1] = their maximum
+__global__ __launch_bounds__(1024) void k_density_finish(uint32_t parts, int64_t n,
+                                                        const double *__restrict__ part_sum,
+                                                        const float *__restrict__ part_max,
+                                                        double *__restrict__ out)
+{
+    __shared__ double dsum[1024 / 64];
+    __shared__ float dmax[1024 / 64];
+    double sum = 0.0;
+    float mx = 0.f;
+    for (uint32_t e = threadIdx.x; e < parts; e += blockDim.x) {
+        sum += part_sum[e];
+        mx = fmaxf(mx, part_max[e]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 64);
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        dsum[threadIdx.x >> 6] = sum;
+        dmax[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        float m = 0.f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            s += dsum[w];
+            m = fmaxf(m, dmax[w]);
+        }
+        out[0] = n ? s / (double)n : 0.0;
+        out[1] = (double)m;
+    }
+}
+
+// out[id] = v[s] for a per-slot float
+__global__ void k_unpermute_scalar(int64_t n, const float *__restrict__ v,
+                                   const uint32_t *__restrict__ id, float *__restrict__ out)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) out[id[s]] = v[s];
+}
+
 // --------------------------------------------- velocity and position update
 __global__ void k_commit(int64_t n, const SceneDev *__restrict__ sc, float4 *__restrict__ x,
                          float4 *__restrict__ v, const float4 *__restrict__ xs,
@@ -1113,6 +1274,72 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     }
     LAUNCH(K_COMMIT, blocks_for(n, bs[K_COMMIT]), bs[K_COMMIT], k_commit, n, b.scenes, b.x[nxt],
            b.v[nxt], b.xs[K & 1], b.err);
+    return hipSuccess;
+}
+
+hipError_t enqueue_density(const StepBuffers &b0, int cur, const LaunchShape &ls,
+                           const DensityBuffers &d, float *rho_id, hipStream_t s)
+{
+    // A fresh counting sort and neighbour search of the current positions
+    // into the free ping-pong half and the density buffers; the step's own
+    // structure, error word and running totals are left alone.
+    StepBuffers b = b0;
+    b.nbr = d.nbr;
+    b.pmeta = d.pmeta;
+    b.pslot = d.pslot;
+    b.tile_rows = d.tile_rows;
+    b.tile_order = d.tile_order;
+    b.tile_start = d.tile_start;
+    b.tile_count = d.tile_count;
+    b.tile_ge = d.tile_ge;
+    b.tile_lvl = d.tile_lvl;
+    b.key = d.key;
+    b.err = d.err;
+    b.totals = d.totals;
+    const int64_t n = b.n;
+    if (n == 0) return hipErrorInvalidValue;
+    const int nxt = cur ^ 1;
+    const int K = b.n_iters;
+    const uint32_t G = b.n_cells, T = b.n_tiles;
+    const uint32_t TX = (T + kXcds - 1) / kXcds * kXcds;
+    const int *bs = ls.block;
+    Timer *tm = nullptr;
+    hipError_t e;
+    LAUNCH(K_LOD_PREDICT, blocks_for(n, 256), 256, k_density_keys, n, b.scenes, b.x[cur],
+           b.xs_pred, b.key_pre, b.ticket, b.cell_count);
+    if ((e = enqueue_scan(b.cell_count, G, b.scan_part, b.cell_start, true, s, tm)) != hipSuccess)
+        return e;
+    LAUNCH(K_SORT_SCATTER, blocks_for(n, bs[K_SORT_SCATTER]), bs[K_SORT_SCATTER], k_sort_scatter,
+           n, b.key_pre, b.ticket, b.cell_start, b.id[cur], b.tmp_src, b.tmp_id);
+    LAUNCH(K_SORT_FINISH, blocks_for(n, bs[K_SORT_FINISH]), bs[K_SORT_FINISH], k_sort_finish, n,
+           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.v[cur], b.xs_pred,
+           b.lvl[cur], b.x[nxt], b.v[nxt], d.xs, b.id[nxt], b.lvl[nxt], b.key, b.err);
+    LAUNCH(K_TILE_PREPARE, blocks_for((int64_t)T * 64, bs[K_TILE_PREPARE]), bs[K_TILE_PREPARE],
+           k_tile_prepare, T, b.scenes, b.tile_scene, b.cell_start, b.lvl[nxt], b.tile_count,
+           b.tile_lvl);
+    if (T <= kFusedTiles) {
+        LAUNCH(K_TILE_TABLES, 1, 1024, k_tile_tables, T, K, b.tile_count, b.tile_lvl, b.tile_start,
+               b.tile_order, b.tile_ge, b.level_part, 0u, b.totals);
+    } else {
+        if ((e = enqueue_scan(b.tile_count, T, b.scan_part, b.tile_start, false, s, tm)) != hipSuccess)
+            return e;
+        LAUNCH(K_LEVEL_COUNT, b.n_level_blocks, kLevelBlock, k_level_count, T, b.tile_lvl,
+               b.level_counts, b.n_level_blocks, K);
+        LAUNCH(K_LEVEL_SCAN, 1, 1024, k_level_scan, b.level_counts, b.n_level_blocks, K, b.tile_ge,
+               b.level_part, 0u, b.totals);
+        LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
+               b.level_counts, b.n_level_blocks, K, b.tile_order);
+    }
+    LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
+           b.tile_ge, b.tile_start, b.cell_start, d.xs, b.lvl[nxt], n, b.nbr_cap, b.nbr, b.pmeta,
+           b.pslot, b.tile_rows, b.err);
+    LAUNCH(K_LAMBDA, TX, kTileThreads, k_density, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
+           b.tile_start, b.tile_count, b.tile_rows, d.xs, n, b.nbr, b.pmeta, b.pslot, d.rho_slot,
+           d.part_sum, d.part_max);
+    LAUNCH(K_COMMIT, 1, 1024, k_density_finish, TX, n, d.part_sum, d.part_max, d.out);
+    if (rho_id)
+        LAUNCH(K_COMMIT, blocks_for(n, 256), 256, k_unpermute_scalar, n, d.rho_slot, b.id[nxt],
+               rho_id);
     return hipSuccess;
 }
 
