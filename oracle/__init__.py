@@ -46,7 +46,10 @@ class Params(ctypes.Structure):
 class Lod(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("levels", ctypes.POINTER(ctypes.c_int32)),
                 ("camera", ctypes.c_double * 3), ("d_near", ctypes.c_double),
-                ("d_far", ctypes.c_double)]
+                ("d_far", ctypes.c_double), ("forward", ctypes.c_double * 3),
+                ("up", ctypes.c_double * 3), ("focal", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("splat", ctypes.c_double)]
 
 
 class Trace(ctypes.Structure):
@@ -146,7 +149,13 @@ class _LodHolder:
             self.lod.levels = _ptr(self.levels, ctypes.c_int32)
         for d in range(3):
             self.lod.camera[d] = float(scene.camera[d])
+            self.lod.forward[d] = float(getattr(scene, "forward", (0, 0, 1))[d])
+            self.lod.up[d] = float(getattr(scene, "up", (0, 1, 0))[d])
         self.lod.d_near, self.lod.d_far = float(scene.d_near), float(scene.d_far)
+        self.lod.focal = float(getattr(scene, "focal", 1.0))
+        w, h = getattr(scene, "image", (1, 1))
+        self.lod.width, self.lod.height = int(w), int(h)
+        self.lod.splat = float(getattr(scene, "splat", 0.0))
 
 
 def levels(scene, x) -> np.ndarray:

@@ -42,6 +42,7 @@
  * Neighbour sums run in ascending particle-ID order, so results do not
  * depend on any storage order.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -63,10 +64,18 @@ typedef struct {
 } orc_params;
 
 typedef struct {
-    int32_t mode;           /* 0 uniform (N_i = n_max), 1 explicit, 2 distance to camera */
+    int32_t mode;           /* 0 uniform (N_i = n_max), 1 explicit, 2 distance to camera,
+                               3 distance to the visible surface */
     const int32_t *levels;  /* explicit: n levels in particle-ID order */
     double camera[3];
     double d_near, d_far;
+    /* distance to the visible surface: the camera frame (unit forward and up
+     * vectors, right = forward x up), focal length in pixels, image size in
+     * pixels and the splat radius of a particle */
+    double forward[3], up[3];
+    double focal;
+    int32_t width, height;
+    double splat;
 } orc_lod;
 
 typedef struct {
@@ -291,8 +300,111 @@ static void clamp_box(const orc_params *p, double *x)
 /* levels (Eq. 8, adaption model of Section 4.1)                       */
 /* ------------------------------------------------------------------ */
 
+/* Level from a distance (DTC and DTVS, Section 4.1): linear map of the
+ * distance range [d_near, d_far] onto the levels n_max .. n_min, decided in
+ * float32 like the kernel. */
+static int32_t level_of_distance(const orc_params *p, const orc_lod *lod, float d)
+{
+    float t = (d - (float)lod->d_near) / ((float)lod->d_far - (float)lod->d_near);
+    if (t < 0.0f) t = 0.0f;
+    if (t > 1.0f) t = 1.0f;
+    int32_t L = p->n_max - (int32_t)floorf(t * (float)(p->n_max - p->n_min + 1));
+    if (L < p->n_min) L = p->n_min;
+    if (L > p->n_max) L = p->n_max;
+    return L;
+}
+
+enum { ORC_MAX_SPLAT = 16 };  /* largest splat radius in pixels */
+
+/* Pinhole projection of x for the DTVS model, in float32 with a fixed
+ * order of operations (the pixel and the depth are integers and minima
+ * decided by floating point).  Returns 0 when the particle is not in front
+ * of the camera by more than its splat radius or its pixel is far outside
+ * the image. */
+typedef struct { int32_t pu, pv, rad; float dist; } orc_proj;
+
+static int dtvs_project(const orc_lod *lod, const double *xi, orc_proj *o)
+{
+    const float f0 = (float)lod->forward[0], f1 = (float)lod->forward[1], f2 = (float)lod->forward[2];
+    const float u0 = (float)lod->up[0], u1 = (float)lod->up[1], u2 = (float)lod->up[2];
+    const float r0 = f1 * u2 - f2 * u1, r1 = f2 * u0 - f0 * u2, r2 = f0 * u1 - f1 * u0;
+    const float qx = (float)xi[0] - (float)lod->camera[0];
+    const float qy = (float)xi[1] - (float)lod->camera[1];
+    const float qz = (float)xi[2] - (float)lod->camera[2];
+    float z = qx * f0;
+    z = z + qy * f1;
+    z = z + qz * f2;
+    const float splat = (float)lod->splat, focal = (float)lod->focal;
+    if (!(z > splat)) return 0;
+    float xr = qx * r0;
+    xr = xr + qy * r1;
+    xr = xr + qz * r2;
+    float yu = qx * u0;
+    yu = yu + qy * u1;
+    yu = yu + qz * u2;
+    float u = focal * xr;
+    u = u / z;
+    u = u + 0.5f * (float)lod->width;
+    float v = focal * yu;
+    v = v / z;
+    v = v + 0.5f * (float)lod->height;
+    const float lim = (float)ORC_MAX_SPLAT + 1.0f;
+    if (!(u > -lim && u < (float)lod->width + lim && v > -lim && v < (float)lod->height + lim)) return 0;
+    o->pu = (int32_t)floorf(u);
+    o->pv = (int32_t)floorf(v);
+    float rf = focal * splat;
+    rf = rf / z;
+    int32_t rad = (int32_t)ceilf(rf);
+    o->rad = rad < ORC_MAX_SPLAT ? rad : ORC_MAX_SPLAT;
+    float d2 = qx * qx;
+    d2 = d2 + qy * qy;
+    d2 = d2 + qz * qz;
+    o->dist = sqrtf(d2);
+    return 1;
+}
+
+/* Distance to the visible surface (DTVS, Section 4.1): every particle in
+ * front of the camera is splatted into a depth image as a square of
+ * (2 rad + 1)^2 pixels around its pixel, keeping the smallest distance to
+ * the camera per pixel; the particles seen at a pixel are the surface, and a
+ * particle's distance to the visible surface is its own distance minus the
+ * depth at its pixel.  Particles behind the camera or outside the image get
+ * the largest distance (lowest level). */
+static int levels_dtvs(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+{
+    const int32_t W = lod->width, H = lod->height;
+    if (W < 1 || H < 1) return ORC_ERR_ARG;
+    float *depth = (float *)malloc(sizeof(float) * (size_t)W * (size_t)H);
+    if (!depth) return ORC_ERR_MEM;
+    for (int64_t e = 0; e < (int64_t)W * H; ++e) depth[e] = INFINITY;
+    for (int32_t j = 0; j < p->n; ++j) {
+        orc_proj o;
+        if (!dtvs_project(lod, x + 3 * (int64_t)j, &o)) continue;
+        for (int32_t b = o.pv - o.rad; b <= o.pv + o.rad; ++b)
+            for (int32_t a = o.pu - o.rad; a <= o.pu + o.rad; ++a)
+                if (a >= 0 && a < W && b >= 0 && b < H && o.dist < depth[(int64_t)b * W + a])
+                    depth[(int64_t)b * W + a] = o.dist;
+    }
+    for (int32_t i = 0; i < p->n; ++i) {
+        orc_proj o;
+        float d = FLT_MAX;
+        if (dtvs_project(lod, x + 3 * (int64_t)i, &o) && o.pu >= 0 && o.pu < W && o.pv >= 0 && o.pv < H)
+            d = o.dist - depth[(int64_t)o.pv * W + o.pu];
+        lev[i] = level_of_distance(p, lod, d);
+    }
+    free(depth);
+    return ORC_OK;
+}
+
 int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
 {
+    if (lod->mode == 3) {
+        int rc = levels_dtvs(p, lod, x, lev);
+        if (rc) return rc;
+        for (int32_t i = 0; i < p->n; ++i)
+            if (lev[i] < 1 || lev[i] < p->n_min || lev[i] > p->n_max) return ORC_ERR_ARG;
+        return ORC_OK;
+    }
     for (int32_t i = 0; i < p->n; ++i) {
         int32_t L;
         if (lod->mode == 0) {
@@ -312,12 +424,7 @@ int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t
             d2 = d2 + dy * dy;
             d2 = d2 + dz * dz;
             float d = sqrtf(d2);
-            float t = (d - (float)lod->d_near) / ((float)lod->d_far - (float)lod->d_near);
-            if (t < 0.0f) t = 0.0f;
-            if (t > 1.0f) t = 1.0f;
-            L = p->n_max - (int32_t)floorf(t * (float)(p->n_max - p->n_min + 1));
-            if (L < p->n_min) L = p->n_min;
-            if (L > p->n_max) L = p->n_max;
+            L = level_of_distance(p, lod, d);
         }
         if (L < 1 || L < p->n_min || L > p->n_max) return ORC_ERR_ARG;
         lev[i] = L;

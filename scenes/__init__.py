@@ -44,6 +44,7 @@ JITTER = 1e-3
 LOD_UNIFORM = 0
 LOD_EXPLICIT = 1
 LOD_DTC = 2
+LOD_DTVS = 3
 
 
 @dataclasses.dataclass
@@ -78,6 +79,15 @@ class Scene:
         default_factory=lambda: np.zeros(3, dtype=F32))
     d_near: float = F32(0.0)
     d_far: float = F32(1.0)
+    # distance to the visible surface: camera frame, focal length (pixels),
+    # image size (pixels) and splat radius of a particle
+    forward: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.array([0.0, 0.0, 1.0], dtype=F32))
+    up: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.array([0.0, 1.0, 0.0], dtype=F32))
+    focal: float = F32(256.0)
+    image: tuple = (256, 256)
+    splat: float = F32(SPACING / 2)
     steps: int = 1
     target: Optional[np.ndarray] = None
 
@@ -91,6 +101,10 @@ class Scene:
         self.h, self.rho0, self.mass = F32(self.h), F32(self.rho0), F32(self.mass)
         self.eps, self.dt = F32(self.eps), F32(self.dt)
         self.d_near, self.d_far = F32(self.d_near), F32(self.d_far)
+        self.forward = np.asarray(self.forward, dtype=F32).reshape(3)
+        self.up = np.asarray(self.up, dtype=F32).reshape(3)
+        self.focal, self.splat = F32(self.focal), F32(self.splat)
+        self.image = (int(self.image[0]), int(self.image[1]))
         if self.dims is None:
             self.dims = grid_dims(self.lo, self.hi, self.h)
         self.dims = np.asarray(self.dims, dtype=np.int32).reshape(3)
@@ -111,6 +125,42 @@ class Scene:
         if n_max is not None:
             s.n_max = int(n_max)
         return s
+
+
+def look_at(camera, target, up=(0.0, 1.0, 0.0)):
+    """Unit forward and up vectors (float32) of a camera at `camera` looking
+    at `target`, with `up` made orthogonal to the view direction."""
+    c = np.asarray(camera, np.float64)
+    f = np.asarray(target, np.float64) - c
+    f /= np.linalg.norm(f)
+    u = np.asarray(up, np.float64)
+    u = u - np.dot(u, f) * f
+    u /= np.linalg.norm(u)
+    return f.astype(F32), u.astype(F32)
+
+
+def with_dtvs(sc: "Scene", camera, target, d_near=0.0, d_far=None, focal=None, image=None,
+              splat=None) -> "Scene":
+    """The scene with distance-to-the-visible-surface levels seen from
+    `camera` looking at `target`.  Defaults: 2.5 pixels per spacing at the
+    nearest particle (splats of about 1.25 pixels' radius, so the visible
+    surface is closed), an image just covering the particles, d_far = 20
+    spacings, splat radius = half a spacing."""
+    f, u = look_at(camera, target)
+    x = sc.x0.astype(np.float64) - np.asarray(camera, np.float64)
+    z = x @ f.astype(np.float64)
+    r = np.cross(f.astype(np.float64), u.astype(np.float64))
+    if focal is None:
+        focal = 2.5 * z.min() / SPACING
+    if image is None:
+        ang = np.max(np.abs(np.stack([x @ r, x @ u.astype(np.float64)], 1)) / z[:, None])
+        side = int(np.ceil(2 * focal * ang)) + 8
+        image = (side, side)
+    d_far = 20 * SPACING if d_far is None else d_far
+    splat = SPACING / 2 if splat is None else splat
+    return dataclasses.replace(sc, lod_mode=LOD_DTVS, camera=np.asarray(camera, F32), forward=f,
+                               up=u, focal=F32(focal), image=tuple(image), splat=F32(splat),
+                               d_near=F32(d_near), d_far=F32(d_far))
 
 
 def grid_dims(lo, hi, h) -> np.ndarray:
