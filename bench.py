@@ -371,6 +371,17 @@ def main(argv=None):
           flush=True)
     with Sim(sc, stream=stream) as sim:
         apbf = _timed_run(sim, steps, warm, stream, torch)
+    # the same tank with distance-to-the-visible-surface levels (the paper's
+    # second adaption model), seen from the same camera
+    # (0..4 m behind the visible surface -> levels 10..5: mean level 7.2 at
+    # t = 0, close to the distance-to-camera run's 7.4)
+    scv = scenes.with_dtvs(sc, camera=sc.camera, target=(3.2, 1.6, 3.2), d_far=4.0)
+    print("[bench] APBF with visible-surface levels", file=sys.stderr, flush=True)
+    with Sim(scv, stream=stream) as sim:
+        try:
+            dtvs = _timed_run(sim, steps, warm, stream, torch)
+        except PbfError as e:
+            dtvs = {"error": str(e)}
     out_pbf = {}
     if not args.no_pbf:
         for N in (10, 5):
@@ -420,6 +431,10 @@ def main(argv=None):
     # the paper's quality measure: average density over all particles after
     # warm-up + timed steps (APBF and PBF(10) from the same initial state)
     line["density"] = {"apbf": apbf["density"]}
+    line["dtvs"] = ({"error": dtvs["error"]} if "error" in dtvs else
+                    {"ms_per_step": round(dtvs["ms_per_step"], 4), "value": round(dtvs["value"], 1),
+                     "mean_levels": round(dtvs["mean_levels"], 4), "density": dtvs["density"]})
+    line["dtvs"]["levels"] = "distance to the visible surface, 0..4 m -> 10..5, same camera"
     if out_pbf:
         line["pbf"] = {str(N): ({"error": r["error"]} if "error" in r else
                                 {"ms_per_step": round(r["ms_per_step"], 4),
@@ -431,6 +446,8 @@ def main(argv=None):
         for N in (10, 5):
             if "error" not in out_pbf[N]:
                 line[f"speedup_vs_pbf{N}"] = round(out_pbf[N]["ms_per_step"] / apbf["ms_per_step"], 4)
+        if "error" not in out_pbf[10] and "error" not in dtvs:
+            line["dtvs"]["speedup_vs_pbf10"] = round(out_pbf[10]["ms_per_step"] / dtvs["ms_per_step"], 4)
     print(json.dumps(line), flush=True)
     return 0
 

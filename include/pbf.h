@@ -78,6 +78,10 @@ typedef enum {
 #define PBF_LOD_EXPLICIT 1 /* N_i from a caller array (particle-ID order) */
 #define PBF_LOD_DTC 2      /* distance to camera, recomputed each step from the
                               positions at the start of the step */
+#define PBF_LOD_DTVS 3     /* distance to the visible surface along the camera
+                              ray, recomputed each step likewise */
+#define PBF_MAX_SPLAT 16   /* largest splat radius in pixels (DTVS) */
+#define PBF_MAX_IMAGE 8192 /* largest DTVS image side in pixels */
 
 /* Per-scene parameters.  All lengths in the same unit as positions. */
 typedef struct pbf_params {
@@ -96,15 +100,33 @@ typedef struct pbf_params {
     uint32_t flags;         /* reserved, must be 0 */
 } pbf_params;
 
-/* Level source (Section 4.1).  DTC: t = clamp((|x - camera| - d_near) /
- * (d_far - d_near), 0, 1), N = clamp(n_max - floor(t (n_max - n_min + 1)),
- * n_min, n_max): near particles iterate n_max times, far ones n_min. */
+/* Level source (Section 4.1).  A distance d is mapped to a level by
+ * t = clamp((d - d_near) / (d_far - d_near), 0, 1),
+ * N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max): near
+ * particles iterate n_max times, far ones n_min.  Both distance models are
+ * evaluated in float32 with one rounding per operation.
+ *
+ * DTC: d = |x - camera|.
+ *
+ * DTVS: the camera is a pinhole at `camera` with unit vectors `forward` and
+ * `up` (right = forward x up), `focal` pixels per unit of depth and a
+ * width x height image.  With q = x - camera, z = q.forward: a particle with
+ * z > splat projects to pixel (floor(focal (q.right) / z + width / 2),
+ * floor(focal (q.up) / z + height / 2)) and is splatted as a square of
+ * (2 r + 1)^2 pixels, r = min(ceil(focal splat / z), PBF_MAX_SPLAT), keeping
+ * per pixel the smallest |q|.  d = |q| minus that depth at the particle's
+ * own pixel (the particles seen there are the surface); particles behind
+ * the camera or outside the image get the lowest level. */
 typedef struct pbf_lod_desc {
     int32_t mode;            /* PBF_LOD_* */
     const uint8_t *levels;   /* EXPLICIT: n levels in [n_min, n_max], particle-ID order */
     int32_t levels_on_device;
-    float camera[3];         /* DTC */
-    float d_near, d_far;     /* DTC: d_far > d_near */
+    float camera[3];         /* DTC, DTVS */
+    float d_near, d_far;     /* DTC, DTVS: d_far > d_near */
+    float forward[3], up[3]; /* DTVS: camera frame, unit length, orthogonal */
+    float focal;             /* DTVS: > 0 */
+    int32_t width, height;   /* DTVS: image in pixels, 1 .. PBF_MAX_IMAGE */
+    float splat;             /* DTVS: splat radius of a particle, >= 0 */
 } pbf_lod_desc;
 
 /* Statistics of the most recent step (read with pbf_stats; synchronises). */

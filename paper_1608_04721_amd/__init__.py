@@ -13,11 +13,11 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (PBF_LOD_DTC, PBF_LOD_EXPLICIT, PBF_LOD_UNIFORM, PBF_MAX_ITERS,  # noqa: F401
-                   PbfLodDesc, PbfParams, PbfStepStats)
+from ._lib import (PBF_LOD_DTC, PBF_LOD_DTVS, PBF_LOD_EXPLICIT, PBF_LOD_UNIFORM,  # noqa: F401
+                   PBF_MAX_ITERS, PbfLodDesc, PbfParams, PbfStepStats)
 
 __all__ = ["Sim", "PbfError", "make_params", "PBF_LOD_UNIFORM", "PBF_LOD_EXPLICIT",
-           "PBF_LOD_DTC", "kernel_names"]
+           "PBF_LOD_DTC", "PBF_LOD_DTVS", "kernel_names", "rollout"]
 
 
 class PbfError(RuntimeError):
@@ -110,7 +110,10 @@ class Sim:
                     self.set_lod(mode, levels=getattr(s, "levels", None),
                                  camera=getattr(s, "camera", None),
                                  d_near=getattr(s, "d_near", 0.0), d_far=getattr(s, "d_far", 1.0),
-                                 scene=i)
+                                 scene=i, forward=getattr(s, "forward", (0.0, 0.0, 1.0)),
+                                 up=getattr(s, "up", (0.0, 1.0, 0.0)),
+                                 focal=getattr(s, "focal", 1.0), image=getattr(s, "image", (1, 1)),
+                                 splat=getattr(s, "splat", 0.0))
 
     # ------------------------------------------------------------ helpers
     def _check(self, st, what):
@@ -136,9 +139,15 @@ class Sim:
         self.close()
 
     # ------------------------------------------------------------ core
-    def set_lod(self, mode, levels=None, camera=None, d_near=0.0, d_far=1.0, scene=0):
+    def set_lod(self, mode, levels=None, camera=None, d_near=0.0, d_far=1.0, scene=0,
+                forward=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), focal=1.0, image=(1, 1), splat=0.0):
         d = PbfLodDesc()
         d.mode = int(mode)
+        for a in range(3):
+            d.forward[a] = float(forward[a])
+            d.up[a] = float(up[a])
+        d.focal, d.splat = float(focal), float(splat)
+        d.width, d.height = int(image[0]), int(image[1])
         keep = None
         if mode == PBF_LOD_EXPLICIT:
             if _is_tensor(levels) and levels.is_cuda:

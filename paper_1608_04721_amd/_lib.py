@@ -25,6 +25,9 @@ PBF_MAX_SCENES = 65535
 PBF_LOD_UNIFORM = 0
 PBF_LOD_EXPLICIT = 1
 PBF_LOD_DTC = 2
+PBF_LOD_DTVS = 3
+PBF_MAX_SPLAT = 16
+PBF_MAX_IMAGE = 8192
 
 c_i32, c_i64, c_u32, c_f32, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                     ctypes.c_float, ctypes.c_void_p)
@@ -39,7 +42,9 @@ class PbfParams(ctypes.Structure):
 
 class PbfLodDesc(ctypes.Structure):
     _fields_ = [("mode", c_i32), ("levels", c_vp), ("levels_on_device", c_i32),
-                ("camera", c_f32 * 3), ("d_near", c_f32), ("d_far", c_f32)]
+                ("camera", c_f32 * 3), ("d_near", c_f32), ("d_far", c_f32),
+                ("forward", c_f32 * 3), ("up", c_f32 * 3), ("focal", c_f32),
+                ("width", c_i32), ("height", c_i32), ("splat", c_f32)]
 
 
 class PbfStepStats(ctypes.Structure):

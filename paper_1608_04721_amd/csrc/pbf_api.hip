@@ -96,6 +96,7 @@ struct pbf_ctx {
     std::vector<float *> ckpt;  // x0, v0, x1, v1, ... (pairs)
     int32_t roll_steps = 0, roll_every = 0;
     bool roll_valid = false;
+    size_t depth_cap = 0;  // pixels allocated in b.depth (DTVS depth images)
     // average-density buffers (allocated by the first pbf_density)
     pbf::DensityBuffers dens{};
     float *dens_rho_id = nullptr;
@@ -231,7 +232,7 @@ void drop_graphs(pbf_ctx *c)
 
 bool fixed_shape(int k)
 {
-    return k == K_SCAN_REDUCE || k == K_SCAN_TOP || k == K_SCAN_APPLY || k == K_LEVEL_COUNT ||
+    return k == K_DEPTH || k == K_SCAN_REDUCE || k == K_SCAN_TOP || k == K_SCAN_APPLY || k == K_LEVEL_COUNT ||
            k == K_LEVEL_SCAN || k == K_LEVEL_SCATTER || k == K_TILE_TABLES;
 }
 
@@ -379,6 +380,7 @@ void pbf_destroy(pbf_ctx *c)
     for (void *p : c->allocs) (void)hipFree(p);
     for (float *p : c->ckpt) (void)hipFree(p);
     for (void *p : c->rs.bufs) (void)hipFree(p);
+    if (c->b.depth) (void)hipFree(c->b.depth);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -559,16 +561,60 @@ pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
         for (int d = 0; d < 3; ++d) s.cam[d] = lod->camera[d];
         s.d_near = lod->d_near;
         s.d_far = lod->d_far;
+    } else if (lod->mode == PBF_LOD_DTVS) {
+        const auto fin = [](float v) { return std::isfinite(v); };
+        if (!finite3(lod->camera) || !finite3(lod->forward) || !finite3(lod->up) ||
+            !fin(lod->focal) || !(lod->focal > 0.f) || !fin(lod->splat) || !(lod->splat >= 0.f) ||
+            !fin(lod->d_near) || !fin(lod->d_far) || !(lod->d_far > lod->d_near))
+            return fail(c, PBF_ERR_INVALID_ARG, "DTVS needs a finite camera frame, focal > 0, "
+                                                "splat >= 0 and d_far > d_near");
+        if (lod->width < 1 || lod->height < 1 || lod->width > PBF_MAX_IMAGE ||
+            lod->height > PBF_MAX_IMAGE)
+            return fail(c, PBF_ERR_INVALID_ARG, "DTVS image size outside [1, PBF_MAX_IMAGE]");
+        for (int d = 0; d < 3; ++d) {
+            s.cam[d] = lod->camera[d];
+            s.fwd[d] = lod->forward[d];
+            s.up[d] = lod->up[d];
+        }
+        s.d_near = lod->d_near;
+        s.d_far = lod->d_far;
+        s.focal = lod->focal;
+        s.splat = lod->splat;
+        s.img_w = lod->width;
+        s.img_h = lod->height;
     } else if (lod->mode != PBF_LOD_UNIFORM) {
         return fail(c, PBF_ERR_INVALID_ARG, "unknown LOD mode");
     }
     s.lod_mode = lod->mode;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->scenes[scene] = s;
+    // lay the depth images of all DTVS scenes out one after another
+    size_t pixels = 0;
+    for (auto &sd : c->scenes) {
+        sd.depth_off = (uint32_t)pixels;
+        if (sd.lod_mode == PBF_LOD_DTVS) pixels += (size_t)sd.img_w * (size_t)sd.img_h;
+    }
+    if (pixels > 0xffffffffull) return fail(c, PBF_ERR_INVALID_ARG, "DTVS images too large in total");
+    if (pixels != c->b.n_depth) drop_graphs(c);  // the step's launches change
+    if (pixels > c->depth_cap) {
+        drop_graphs(c);
+        if (c->b.depth) (void)hipFree(c->b.depth);
+        c->b.depth = nullptr;
+        c->depth_cap = 0;
+        c->b.n_depth = 0;
+        hipError_t e = hipMalloc((void **)&c->b.depth, pixels * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            c->b.depth = nullptr;
+            return hip_fail(c, e, "depth images");
+        }
+        c->depth_cap = pixels;
+    }
+    c->b.n_depth = (uint32_t)pixels;
     if (!lv.empty())
         HIPCHK(c, hipMemcpyAsync(c->b.lev_by_id + c->pid_off[scene], lv.data(), lv.size(),
                                  hipMemcpyHostToDevice, c->stream), "upload levels");
-    HIPCHK(c, hipMemcpyAsync((void *)(c->b.scenes + scene), &c->scenes[scene], sizeof(SceneDev),
-                             hipMemcpyHostToDevice, c->stream), "upload scene");
+    HIPCHK(c, hipMemcpyAsync((void *)c->b.scenes, c->scenes.data(), sizeof(SceneDev) * c->scenes.size(),
+                             hipMemcpyHostToDevice, c->stream), "upload scenes");
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return PBF_OK;
 }

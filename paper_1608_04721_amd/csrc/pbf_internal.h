@@ -62,6 +62,11 @@ struct SceneDev {
     int32_t n_min, n_max;
     int32_t lod_mode;
     float cam[3], d_near, d_far;
+    // distance to the visible surface: camera frame, focal length, image
+    // and splat radius; the scene's depth image starts at depth_off
+    float fwd[3], up[3], focal, splat;
+    int32_t img_w, img_h;
+    uint32_t depth_off;
 };
 
 // Device fault bits, latched in a device word.
@@ -73,7 +78,8 @@ enum : uint32_t {
 
 // Kernel classes (launch shape and profiling unit).
 enum Kernel : int {
-    K_LOD_PREDICT = 0,
+    K_DEPTH = 0,
+    K_LOD_PREDICT,
     K_SCAN_REDUCE,
     K_SCAN_TOP,
     K_SCAN_APPLY,
@@ -140,6 +146,8 @@ struct StepBuffers {
     uint32_t *err;
     uint32_t *level_part;    // per lod_predict block: sum of N_i
     unsigned long long *totals;  // [0] sum of N_i over steps, [1] steps
+    uint32_t *depth;         // depth images of the DTVS scenes (float bits)
+    uint32_t n_depth;        // their pixels in total (0: no DTVS scene)
 };
 
 struct LaunchShape {

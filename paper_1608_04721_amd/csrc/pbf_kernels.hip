@@ -31,11 +31,11 @@
 namespace pbf {
 
 const char *const kKernelNames[K_COUNT] = {
-    "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
+    "depth",        "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
     "sort_finish",  "tile_prepare", "level_count", "level_scan",  "level_scatter",
     "tile_tables",  "neighbours",  "lambda",       "update",      "commit"};
 
-const int kDefaultBlock[K_COUNT] = {256,          kScanBlock,   1024,         kScanBlock,
+const int kDefaultBlock[K_COUNT] = {256,          256,          kScanBlock,   1024,         kScanBlock,
                                     256,          256,          256,          kLevelBlock,
                                     1024,         kLevelBlock,  1024,         kNbrThreads,
                                     kTileThreads, kTileThreads, 256};
@@ -96,10 +96,20 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi)
     return fminf(fmaxf(v, lo), hi);
 }
 
-// Distance-to-camera level (linear map of the distance to the level range,
-// Section 4.1).  The level is an integer chosen by floating point, so the
-// operations are fixed: float32, no contraction into FMAs, correctly rounded
-// square root and division, in this order.
+// Level from a distance (linear map of the distance range onto the level
+// range, Section 4.1).  The level is an integer chosen by floating point, so
+// the operations are fixed: float32, no contraction into FMAs, correctly
+// rounded square root and division, in this order.
+__device__ __forceinline__ int level_of_distance(float d, float d_near, float d_far, int nmin, int nmax)
+{
+#pragma clang fp contract(off)
+    float t = (d - d_near) / (d_far - d_near);
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    const int L = nmax - (int)floorf(t * (float)(nmax - nmin + 1));
+    return min(max(L, nmin), nmax);
+}
+
+// Distance-to-camera level (DTC)
 __device__ __forceinline__ int dtc_level(float x, float y, float z, float cx, float cy, float cz,
                                          float d_near, float d_far, int nmin, int nmax)
 {
@@ -108,11 +118,100 @@ __device__ __forceinline__ int dtc_level(float x, float y, float z, float cx, fl
     float d2 = dx * dx;
     d2 = d2 + dy * dy;
     d2 = d2 + dz * dz;
-    const float d = sqrtf(d2);
-    float t = (d - d_near) / (d_far - d_near);
-    t = fminf(fmaxf(t, 0.f), 1.f);
-    const int L = nmax - (int)floorf(t * (float)(nmax - nmin + 1));
-    return min(max(L, nmin), nmax);
+    return level_of_distance(sqrtf(d2), d_near, d_far, nmin, nmax);
+}
+
+// Pinhole projection for the distance-to-the-visible-surface model (DTVS):
+// pixel, splat radius in pixels and distance to the camera, in float32 with
+// a fixed order of operations (pixels and depth minima are decided by
+// floating point).  False when the particle is not in front of the camera
+// by more than its splat radius or its pixel is far outside the image.
+struct Proj {
+    int pu, pv, rad;
+    float dist;
+};
+
+__device__ __forceinline__ bool dtvs_project(const SceneDev &S, float x, float y, float z, Proj &o)
+{
+#pragma clang fp contract(off)
+    const float f0 = S.fwd[0], f1 = S.fwd[1], f2 = S.fwd[2];
+    const float u0 = S.up[0], u1 = S.up[1], u2 = S.up[2];
+    const float r0 = f1 * u2 - f2 * u1, r1 = f2 * u0 - f0 * u2, r2 = f0 * u1 - f1 * u0;
+    const float qx = x - S.cam[0], qy = y - S.cam[1], qz = z - S.cam[2];
+    float zd = qx * f0;
+    zd = zd + qy * f1;
+    zd = zd + qz * f2;
+    if (!(zd > S.splat)) return false;
+    float xr = qx * r0;
+    xr = xr + qy * r1;
+    xr = xr + qz * r2;
+    float yu = qx * u0;
+    yu = yu + qy * u1;
+    yu = yu + qz * u2;
+    float u = S.focal * xr;
+    u = u / zd;
+    u = u + 0.5f * (float)S.img_w;
+    float v = S.focal * yu;
+    v = v / zd;
+    v = v + 0.5f * (float)S.img_h;
+    const float lim = (float)PBF_MAX_SPLAT + 1.0f;
+    if (!(u > -lim && u < (float)S.img_w + lim && v > -lim && v < (float)S.img_h + lim)) return false;
+    o.pu = (int)floorf(u);
+    o.pv = (int)floorf(v);
+    float rf = S.focal * S.splat;
+    rf = rf / zd;
+    o.rad = min((int)ceilf(rf), PBF_MAX_SPLAT);
+    float d2 = qx * qx;
+    d2 = d2 + qy * qy;
+    d2 = d2 + qz * qz;
+    o.dist = sqrtf(d2);
+    return true;
+}
+
+// DTVS level: the particle's distance to the camera minus the depth of the
+// visible surface at its pixel; the lowest level when it is not seen
+__device__ __forceinline__ int dtvs_level(const SceneDev &S, const uint32_t *__restrict__ depth,
+                                          float x, float y, float z)
+{
+#pragma clang fp contract(off)
+    Proj o;
+    float d = 3.402823466e38f;  // largest float: lowest level
+    if (dtvs_project(S, x, y, z, o) && o.pu >= 0 && o.pu < S.img_w && o.pv >= 0 && o.pv < S.img_h)
+        d = o.dist - __uint_as_float(depth[S.depth_off + (uint32_t)o.pv * (uint32_t)S.img_w + (uint32_t)o.pu]);
+    return level_of_distance(d, S.d_near, S.d_far, S.n_min, S.n_max);
+}
+
+// Depth images of the DTVS scenes: clear to +infinity, then every particle
+// of such a scene keeps the minimum of its distance over its splat square
+// (an unsigned minimum of the float bits, which orders non-negative floats;
+// the result does not depend on the order of the atomics)
+__global__ void k_depth_clear(uint32_t m, uint32_t *__restrict__ depth)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) depth[e] = 0x7f800000u;
+}
+
+__global__ void k_depth_splat(int64_t n, const SceneDev *__restrict__ sc,
+                              const float4 *__restrict__ x, uint32_t *__restrict__ depth)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float4 xi = x[s];
+    const SceneDev &S = sc[__float_as_int(xi.w)];
+    if (S.lod_mode != PBF_LOD_DTVS) return;
+    Proj o;
+    if (!dtvs_project(S, xi.x, xi.y, xi.z, o)) return;
+    const uint32_t bits = __float_as_uint(o.dist);
+    const int a0 = max(o.pu - o.rad, 0), a1 = min(o.pu + o.rad, S.img_w - 1);
+    const int b0 = max(o.pv - o.rad, 0), b1 = min(o.pv + o.rad, S.img_h - 1);
+    // the particles along one ray all land on the same pixels: a plain read
+    // first, and an atomic only where it can still lower the value (a stale
+    // read costs one needless atomic; the minimum is the same either way)
+    for (int b = b0; b <= b1; ++b)
+        for (int a = a0; a <= a1; ++a) {
+            uint32_t *px = &depth[S.depth_off + (uint32_t)b * (uint32_t)S.img_w + (uint32_t)a];
+            if (bits < *px) atomicMin(px, bits);  // values only fall: a stale read is safe
+        }
 }
 
 // Ticket of a particle inside its cell from the counting-sort histogram (all
@@ -146,6 +245,7 @@ __device__ __forceinline__ uint32_t cell_ticket(uint32_t k, bool valid, uint32_t
 __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
                               const float4 *__restrict__ x, float4 *__restrict__ v,
                               const uint32_t *__restrict__ id, const uint8_t *__restrict__ lev_by_id,
+                              const uint32_t *__restrict__ depth,
                               float4 *__restrict__ xs_pred, uint8_t *__restrict__ lvl,
                               uint32_t *__restrict__ key, uint32_t *__restrict__ ticket,
                               uint32_t *__restrict__ cell_count,
@@ -166,6 +266,8 @@ __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
         } else if (S.lod_mode == PBF_LOD_DTC) {
             L = dtc_level(xi.x, xi.y, xi.z, S.cam[0], S.cam[1], S.cam[2], S.d_near, S.d_far,
                           nmin, nmax);
+        } else if (S.lod_mode == PBF_LOD_DTVS) {
+            L = dtvs_level(S, depth, xi.x, xi.y, xi.z);
         } else {
             L = nmax;
         }
@@ -1220,10 +1322,14 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     const int *bs = ls.block;
     hipError_t e;
 
+    if (b.n_depth) {  // depth images of the distance-to-the-visible-surface scenes
+        LAUNCH(K_DEPTH, blocks_for(b.n_depth, 256), 256, k_depth_clear, b.n_depth, b.depth);
+        LAUNCH(K_DEPTH, blocks_for(n, 256), 256, k_depth_splat, n, b.scenes, b.x[cur], b.depth);
+    }
     // cell_count is all zero here: cleared at creation, and by the cell scan
     // of every step once it has read the counts
     LAUNCH(K_LOD_PREDICT, blocks_for(n, bs[K_LOD_PREDICT]), bs[K_LOD_PREDICT], k_lod_predict, n,
-           b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.xs_pred, b.lvl[cur],
+           b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.depth, b.xs_pred, b.lvl[cur],
            b.key_pre, b.ticket, b.cell_count, b.level_part);
     if ((e = enqueue_scan(b.cell_count, G, b.scan_part, b.cell_start, true, s, tm)) != hipSuccess)
         return e;
