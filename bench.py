@@ -232,6 +232,7 @@ def run_batch(args, torch, stream):
                    "value": round(serial["value"], 1)},
         "speedup_vs_serial": round(serial["ms_per_step"] / batched["ms_per_step"], 4),
         "mean_levels": round(batched["mean_levels"], 4),
+        "density": batched["density"],
     }
 
 

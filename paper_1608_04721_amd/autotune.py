@@ -16,6 +16,7 @@ from __future__ import annotations
 import hashlib
 import json
 import os
+import sys
 from pathlib import Path
 from typing import Dict, Optional
 
@@ -107,7 +108,7 @@ def tune(sim, steps: int = 3, use_cache: bool = True, verbose: bool = False) -> 
         best[kname] = pick
         if verbose:
             print(f"[tune] {kname}: " + ", ".join(f"{t}:{ms * 1e3:.1f}us" for t, ms in timings.items())
-                  + f" -> {pick}", flush=True)
+                  + f" -> {pick}", file=sys.stderr, flush=True)
     if use_cache:
         table = _load()
         table[key] = best
