@@ -62,18 +62,23 @@ __device__ __forceinline__ uint32_t level_of(uint32_t meta)
     return meta_level(meta);
 }
 
-// Decode the step's neighbour codes into slots, slot[q * n + p] (one tile
-// per workgroup, same tables as the forward kernels).
+// Decode the step's neighbour codes into slots, slot[q * n + p] (a tile's
+// own particles over gridDim.x / tiles workgroups, same tables as the
+// forward kernels).
 __global__ __launch_bounds__(kNbrThreads) void k_adj_decode(
-    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
+    uint32_t tiles, const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
     const uint32_t *__restrict__ rows, int64_t n, const uint4 *__restrict__ nbr,
     const uint32_t *__restrict__ pmeta, uint32_t *__restrict__ slot)
 {
     __shared__ uint32_t bnd[kBndWords];
     __shared__ uint32_t base[kStageRows + 1];
-    if (blockIdx.x >= tile_ge[1]) return;
-    const uint32_t tile = tile_order[blockIdx.x];
+    const uint32_t b = blockIdx.x % tiles;
+    if (b >= tile_ge[1]) return;
+    const uint32_t tile = tile_order[b];
+    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    uint32_t first, last;
+    if (!split_part(nown, blockIdx.x / tiles, gridDim.x / tiles, first, last)) return;
     for (int e = threadIdx.x; e < kRowWords; e += blockDim.x) {
         const uint32_t w = rows[(size_t)tile * kRowWords + e];
         if (e < kBndWords) bnd[e] = w;
@@ -81,12 +86,12 @@ __global__ __launch_bounds__(kNbrThreads) void k_adj_decode(
     }
     __syncthreads();
     const bool fits = base[kStageRows] <= (uint32_t)kStageCap;
-    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
-    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t cnt = pmeta[p] & kMetaCount;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
         for (uint32_t q = 0; q < cnt; ++q) {
-            const uint4 v = nbr[(size_t)(q >> 3) * n + p];
+            if ((q & 7u) == 0) v = nbr[(size_t)(q >> 3) * n + p];  // one load per group of 8 codes
             const uint32_t w = (q & 7u) < 4u ? ((q & 7u) < 2u ? v.x : v.y) : ((q & 7u) < 6u ? v.z : v.w);
             const uint32_t c = (q & 1u) ? (w >> 16) : (w & 0xffffu);
             uint32_t s;
@@ -347,29 +352,32 @@ hipError_t enqueue_adjoint_step(const StepBuffers &b, const StepRecord &r, const
     const int64_t n = b.n;
     if (n == 0) return hipSuccess;
     const int K = b.n_iters;
-    const unsigned gb = blocks(n, 256);
-    hipLaunchKernelGGL(k_adj_decode, dim3(b.n_tiles), dim3(kNbrThreads), 0, s, r.tile_order,
-                       r.tile_ge, r.tile_start, r.tile_count, r.tile_rows, n, r.nbr, r.pmeta,
-                       w.nslot);
+    // per-particle kernels: one wave per workgroup below 2^18 particles, so
+    // that a small rollout still spreads over every CU
+    const int tb = n >= (int64_t(1) << 18) ? 256 : 64;
+    const unsigned gb = blocks(n, tb);
+    hipLaunchKernelGGL(k_adj_decode, dim3(b.n_tiles * tile_split(b.n_tiles)), dim3(kNbrThreads), 0,
+                       s, b.n_tiles, r.tile_order, r.tile_ge, r.tile_start, r.tile_count,
+                       r.tile_rows, n, r.nbr, r.pmeta, w.nslot);
     ACHK(hipGetLastError());
-    hipLaunchKernelGGL(k_adj_commit, dim3(gb), dim3(256), 0, s, n, b.scenes, b.id_scene, r.id,
+    hipLaunchKernelGGL(k_adj_commit, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene, r.id,
                        ax_in, av_in, w.zb, w.xb, w.lb);
     ACHK(hipGetLastError());
     for (int k = K - 1; k >= 0; --k) {
-        hipLaunchKernelGGL(k_adj_clamp, dim3(gb), dim3(256), 0, s, k, n, b.scenes, b.id_scene,
+        hipLaunchKernelGGL(k_adj_clamp, dim3(gb), dim3(tb), 0, s, k, n, b.scenes, b.id_scene,
                            r.id, r.lvl, r.snap[k + 1], w.zb, w.dpb);
         ACHK(hipGetLastError());
-        hipLaunchKernelGGL(k_adj_dp, dim3(gb), dim3(256), 0, s, n, b.scenes, b.id_scene, r.id,
+        hipLaunchKernelGGL(k_adj_dp, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene, r.id,
                            r.pslot, r.pmeta, w.nslot, r.snap[k], w.dpb, w.zb, w.lb);
         ACHK(hipGetLastError());
-        hipLaunchKernelGGL(k_adj_lambda, dim3(gb), dim3(256), 0, s, k, n, b.scenes, b.id_scene,
+        hipLaunchKernelGGL(k_adj_lambda, dim3(gb), dim3(tb), 0, s, k, n, b.scenes, b.id_scene,
                            r.id, r.pslot, r.pmeta, w.nslot, r.snap[k], w.lb, w.gc, w.sb);
         ACHK(hipGetLastError());
-        hipLaunchKernelGGL(k_adj_constraint, dim3(gb), dim3(256), 0, s, n, b.scenes, b.id_scene,
+        hipLaunchKernelGGL(k_adj_constraint, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene,
                            r.id, r.pslot, r.pmeta, w.nslot, r.snap[k], w.gc, w.sb, w.zb);
         ACHK(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_adj_predict, dim3(gb), dim3(256), 0, s, n, b.scenes, b.id_scene, r.id,
+    hipLaunchKernelGGL(k_adj_predict, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene, r.id,
                        r.snap[0], w.zb, w.xb, ax_out, av_out);
     return hipGetLastError();
 }

@@ -104,6 +104,27 @@ constexpr int kLevelBlock = 256;  // items per level-bucketing block (fixed: 4 w
 constexpr int kScanItems = 8;     // items per thread in the exclusive scans
 constexpr int kScanBlock = 256;   // threads of a scan block (2048 items)
 constexpr uint32_t kFusedTiles = 16384;  // up to this many tiles, one workgroup does the tile tables
+constexpr uint32_t kSplitTarget = 1024;  // tile workgroups that fill the chip (4 per CU)
+constexpr uint32_t kMaxSplit = 8;        // at most this many workgroups per tile (64 particles each)
+
+// Workgroups per tile for a grid of `tiles` tiles: with few tiles, each
+// tile's own particles are split over up to kMaxSplit workgroups so that the
+// grid still fills the chip.
+inline uint32_t tile_split(uint32_t tiles)
+{
+    return tiles >= kSplitTarget ? 1u : (kSplitTarget / tiles < kMaxSplit ? kSplitTarget / tiles : kMaxSplit);
+}
+
+// Part `sub` of `parts` of a tile's nown own particles, cut at wave
+// boundaries: [first, last); false when the part is empty.
+__device__ __forceinline__ bool split_part(uint32_t nown, uint32_t sub, uint32_t parts, uint32_t &first,
+                                           uint32_t &last)
+{
+    const uint32_t chunk = ((nown + parts - 1) / parts + 63u) & ~63u;
+    first = sub * chunk;
+    last = nown < first + chunk ? nown : first + chunk;
+    return first < last;
+}
 
 // Every buffer one step touches.  Storage ("slot") order is the cell order
 // of the last counting sort.  Per-particle solver data ("p" order) is laid

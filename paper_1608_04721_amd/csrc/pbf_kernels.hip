@@ -766,11 +766,11 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                                                     const float4 *__restrict__ xs, float h2, uint32_t p0,
                                                     int64_t n, int cap, const uint8_t *__restrict__ lvl,
                                                     uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta,
-                                                    uint32_t *__restrict__ pslot)
+                                                    uint32_t *__restrict__ pslot, uint32_t first,
+                                                    uint32_t last)
 {
-    const uint32_t nown = tb.own[kOwnRows];
     uint32_t bad = 0;
-    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
         int o = 0;
         while (tb.own[o + 1] <= pl) ++o;
         const int sy = 1 + o % kTileEdge, sz = 1 + o / kTileEdge;
@@ -859,32 +859,39 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
     return bad;
 }
 
+template <bool SPLIT>
 __global__ __launch_bounds__(kNbrThreads) void k_neighbours(
     const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ cell_start,
     const float4 *__restrict__ xs, const uint8_t *__restrict__ lvl, int64_t n, int cap,
     uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta, uint32_t *__restrict__ pslot,
-    uint32_t *__restrict__ rows, uint32_t *__restrict__ err)
+    const uint32_t *__restrict__ tile_count, uint32_t *__restrict__ rows,
+    uint32_t *__restrict__ err, uint32_t tx)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;
-    if (!xcd_slot(blockIdx.x, tile_ge[1], slot)) return;  // empty tiles are listed last
+    if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[1], slot)) return;  // empty tiles last
     const uint32_t tile = tile_order[slot];
+    uint32_t first = 0, last = 0;
+    if (SPLIT && !split_part(tile_count[tile], blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     const TileLoc t = tile_locate(tile, tile_scene, sc);
     const bool fits = tile_tables(t, cell_start, tb);
+    if (!SPLIT) last = tb.own[kOwnRows];
     // keep the tables for the solver passes of this step
-    for (int e = threadIdx.x; e < kRowWords; e += blockDim.x)
-        rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
+    if (first == 0)
+        for (int e = threadIdx.x; e < kRowWords; e += blockDim.x)
+            rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
     const float h2 = t.S->h2;
     const uint32_t p0 = tile_start[tile];
     uint32_t bad;
     if (fits) {
         tile_stage(tb, xs, stage);
-        bad = tile_neighbours<true>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot);
+        bad = tile_neighbours<true>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot, first, last);
     } else {
-        bad = tile_neighbours<false>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot);
+        bad = tile_neighbours<false>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot, first,
+                                     last);
     }
     if (bad) atomicOr(err, bad);
 }
@@ -965,11 +972,11 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
                                             int64_t n, const uint4 *__restrict__ nbr,
                                             const uint32_t *__restrict__ pmeta,
                                             const uint32_t *__restrict__ pslot, uint32_t p0,
-                                            uint32_t nown)
+                                            uint32_t nown, uint32_t first, uint32_t last)
 {
     const float h = S.h, h2 = S.h2, cg = S.c_grad, h6 = S.h6, crho = S.c_rho, cs = S.c_s,
                 eps = S.eps;
-    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t meta = pmeta[p];
         const uint32_t i = pslot[p];  // independent loads, issued together
@@ -998,25 +1005,28 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
 
 // lambda_i of the tile's active particles, written to xs[i].w; neighbours
 // read only xyz of the same buffer.
+template <bool SPLIT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_lambda(
     int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
     const uint32_t *__restrict__ rows, float4 *__restrict__ xs, int64_t n,
     const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
-    const uint32_t *__restrict__ pslot)
+    const uint32_t *__restrict__ pslot, uint32_t tx)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;
-    if (!xcd_slot(blockIdx.x, tile_ge[k + 1], slot)) return;  // tiles with an active particle
+    if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[k + 1], slot)) return;  // active tiles
     const uint32_t tile = tile_order[slot];
     const SceneDev &S = sc[tile_scene[tile]];
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    uint32_t first = 0, last = nown;
+    if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     if (stage_rows(rows, tile, xs, tb, stage))
-        tile_lambda<true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown);
+        tile_lambda<true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last);
     else
-        tile_lambda<false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown);
+        tile_lambda<false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last);
 }
 
 // Delta p_i (Eq. 7) with the wall contact (clamp) for the active own
@@ -1029,12 +1039,12 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
                                             const uint4 *__restrict__ nbr,
                                             const uint32_t *__restrict__ pmeta,
                                             const uint32_t *__restrict__ pslot, uint32_t p0,
-                                            uint32_t nown)
+                                            uint32_t nown, uint32_t first, uint32_t last)
 {
     const float h = S.h, cg = S.c_grad, sr = S.inv_rho0;
     const float lo0 = S.lo[0], lo1 = S.lo[1], lo2 = S.lo[2];
     const float hi0 = S.hi[0], hi1 = S.hi[1], hi2 = S.hi[2];
-    for (uint32_t pl = threadIdx.x; pl < nown; pl += blockDim.x) {
+    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t meta = pmeta[p];
         const uint32_t i = pslot[p];  // independent loads, issued together
@@ -1067,25 +1077,29 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
 // (Jacobi).  Particles that finished with this iteration (N_i == k) copy
 // position and lambda across, so that both buffers hold their final values
 // from now on.
+template <bool SPLIT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_update(
     int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
     const uint32_t *__restrict__ rows, const float4 *__restrict__ xs_in,
     float4 *__restrict__ xs_out, int64_t n, const uint4 *__restrict__ nbr,
-    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot)
+    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot, uint32_t tx)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;  // tiles with a particle of level >= k
-    if (!xcd_slot(blockIdx.x, tile_ge[k > 1 ? k : 1], slot)) return;
+    if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[k > 1 ? k : 1], slot)) return;
     const uint32_t tile = tile_order[slot];
     const SceneDev &S = sc[tile_scene[tile]];
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    uint32_t first = 0, last = nown;
+    if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     if (stage_rows(rows, tile, xs_in, tb, stage))
-        tile_update<true>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown);
+        tile_update<true>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown, first, last);
     else
-        tile_update<false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown);
+        tile_update<false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown, first,
+                           last);
 }
 
 // ------------------------------------------------ average density
@@ -1319,6 +1333,7 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     const int K = b.n_iters;
     const uint32_t G = b.n_cells, T = b.n_tiles;
     const uint32_t TX = (T + kXcds - 1) / kXcds * kXcds;  // tile grids, see xcd_slot
+    const uint32_t SPLIT = tile_split(TX);
     const int *bs = ls.block;
     hipError_t e;
 
@@ -1355,21 +1370,27 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
         LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
                b.level_counts, b.n_level_blocks, K, b.tile_order);
     }
-    LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
-           b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap, b.nbr,
-           b.pmeta, b.pslot, b.tile_rows, b.err);
+    // the split variants only where the grid has room for them: the plain
+    // ones need not wait for the tile's count before staging
+#define TILE_LAUNCH(KID, KERNEL, ...)                                                       \
+    do {                                                                                  \
+        if (SPLIT > 1) LAUNCH(KID, TX * SPLIT, bs[KID], KERNEL<true>, __VA_ARGS__, TX);   \
+        else LAUNCH(KID, TX, bs[KID], KERNEL<false>, __VA_ARGS__, TX);                    \
+    } while (0)
+    TILE_LAUNCH(K_NEIGHBOURS, k_neighbours, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
+                b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap, b.nbr, b.pmeta,
+                b.pslot, b.tile_count, b.tile_rows, b.err);
     for (int k = 0; k < K; ++k) {
         float4 *xin = b.xs[k & 1], *xout = b.xs[(k + 1) & 1];
-        LAUNCH(K_LAMBDA, TX, bs[K_LAMBDA], k_lambda, k, b.scenes, b.tile_scene, b.tile_order,
-               b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr, b.pmeta,
-               b.pslot);
+        TILE_LAUNCH(K_LAMBDA, k_lambda, k, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
+                    b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr, b.pmeta, b.pslot);
         if (rec && (e = hipMemcpyAsync(rec->snap[k], xin, sizeof(float4) * n,
                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;
-        LAUNCH(K_UPDATE, TX, bs[K_UPDATE], k_update, k, b.scenes, b.tile_scene, b.tile_order,
-               b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, xout, n, b.nbr, b.pmeta,
-               b.pslot);
+        TILE_LAUNCH(K_UPDATE, k_update, k, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
+                    b.tile_start, b.tile_count, b.tile_rows, xin, xout, n, b.nbr, b.pmeta, b.pslot);
     }
+#undef TILE_LAUNCH
     if (rec) {
         if ((e = hipMemcpyAsync(rec->snap[K], b.xs[K & 1], sizeof(float4) * n,
                                 hipMemcpyDeviceToDevice, s)) != hipSuccess ||
@@ -1436,9 +1457,9 @@ hipError_t enqueue_density(const StepBuffers &b0, int cur, const LaunchShape &ls
         LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
                b.level_counts, b.n_level_blocks, K, b.tile_order);
     }
-    LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours, b.scenes, b.tile_scene, b.tile_order,
-           b.tile_ge, b.tile_start, b.cell_start, d.xs, b.lvl[nxt], n, b.nbr_cap, b.nbr, b.pmeta,
-           b.pslot, b.tile_rows, b.err);
+    LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours<false>, b.scenes, b.tile_scene,
+           b.tile_order, b.tile_ge, b.tile_start, b.cell_start, d.xs, b.lvl[nxt], n, b.nbr_cap,
+           b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX);
     LAUNCH(K_LAMBDA, TX, kTileThreads, k_density, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
            b.tile_start, b.tile_count, b.tile_rows, d.xs, n, b.nbr, b.pmeta, b.pslot, d.rho_slot,
            d.part_sum, d.part_max);
