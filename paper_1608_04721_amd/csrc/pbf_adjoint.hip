@@ -62,17 +62,40 @@ __device__ __forceinline__ uint32_t level_of(uint32_t meta)
     return meta_level(meta);
 }
 
+// The gather kernels below give each particle L consecutive lanes of a wave
+// (L divides 64): lane `sub` takes neighbours sub, sub + L, ..., and the L
+// partial sums are combined in a fixed butterfly order, so the result is
+// deterministic.  Lane 0 of the group writes.
+template <int L>
+__device__ __forceinline__ float group_sum(float v)
+{
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int L>
+__device__ __forceinline__ bool group_of(int64_t n, int64_t &p, uint32_t &sub)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    p = t / L;
+    sub = (uint32_t)(t % L);
+    return p < n;
+}
+
 // Decode the step's neighbour codes into slots, slot[q * n + p] (a tile's
 // own particles over gridDim.x / tiles workgroups, same tables as the
-// forward kernels).
+// forward kernels).  A thread takes one group of 8 codes of one particle;
+// a staged code is an LDS stage index, turned into its slot by a table of
+// the whole stage built first.
 __global__ __launch_bounds__(kNbrThreads) void k_adj_decode(
     uint32_t tiles, const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
-    const uint32_t *__restrict__ rows, int64_t n, const uint4 *__restrict__ nbr,
+    const uint32_t *__restrict__ rows, int64_t n, uint32_t groups, const uint4 *__restrict__ nbr,
     const uint32_t *__restrict__ pmeta, uint32_t *__restrict__ slot)
 {
     __shared__ uint32_t bnd[kBndWords];
     __shared__ uint32_t base[kStageRows + 1];
+    __shared__ uint32_t table[kStageCap];
     const uint32_t b = blockIdx.x % tiles;
     if (b >= tile_ge[1]) return;
     const uint32_t tile = tile_order[b];
@@ -86,27 +109,27 @@ __global__ __launch_bounds__(kNbrThreads) void k_adj_decode(
     }
     __syncthreads();
     const bool fits = base[kStageRows] <= (uint32_t)kStageCap;
-    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
-        const size_t p = p0 + pl;
+    if (fits) {
+        for (int r = 0; r < kStageRows; ++r)
+            for (uint32_t c = base[r] + threadIdx.x; c < base[r + 1]; c += blockDim.x)
+                table[c] = bnd[r * (kStageEdge + 1)] + (c - base[r]);
+        __syncthreads();
+    }
+    const uint32_t m = last - first;
+    for (uint32_t t = threadIdx.x; t < m * groups; t += blockDim.x) {
+        const uint32_t g = t / m;
+        const size_t p = p0 + first + (t - g * m);
         const uint32_t cnt = pmeta[p] & kMetaCount;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        for (uint32_t q = 0; q < cnt; ++q) {
-            if ((q & 7u) == 0) v = nbr[(size_t)(q >> 3) * n + p];  // one load per group of 8 codes
-            const uint32_t w = (q & 7u) < 4u ? ((q & 7u) < 2u ? v.x : v.y) : ((q & 7u) < 6u ? v.z : v.w);
-            const uint32_t c = (q & 1u) ? (w >> 16) : (w & 0xffffu);
-            uint32_t s;
-            if (fits) {
-                int lo = 0, hi = kStageRows - 1;  // row r with base[r] <= c < base[r + 1]
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (base[mid] <= c) lo = mid;
-                    else hi = mid - 1;
-                }
-                s = bnd[lo * (kStageEdge + 1)] + (c - base[lo]);
-            } else {
-                s = bnd[(c >> kSegOffBits) * (kStageEdge + 1)] + (c & ((1u << kSegOffBits) - 1));
-            }
-            slot[(size_t)q * n + p] = s;
+        if (8 * g >= cnt) continue;
+        const uint4 v = nbr[(size_t)g * n + p];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        const uint32_t top = cnt - 8 * g < 8 ? cnt - 8 * g : 8;
+        for (uint32_t u = 0; u < top; ++u) {
+            const uint32_t c = (u & 1u) ? (w[u >> 1] >> 16) : (w[u >> 1] & 0xffffu);
+            const uint32_t s = fits ? table[c]
+                                    : bnd[(c >> kSegOffBits) * (kStageEdge + 1)] +
+                                          (c & ((1u << kSegOffBits) - 1));
+            slot[(size_t)(8 * g + u) * n + p] = s;
         }
     }
 }
@@ -154,6 +177,7 @@ __global__ void k_adj_clamp(int k, int64_t n, const SceneDev *__restrict__ sc,
 }
 
 // (b): lambda and position adjoints from the corrections
+template <int L>
 __global__ void k_adj_dp(int64_t n, const SceneDev *__restrict__ sc,
                          const uint32_t *__restrict__ id_scene, const uint32_t *__restrict__ id,
                          const uint32_t *__restrict__ pslot, const uint32_t *__restrict__ pmeta,
@@ -161,8 +185,9 @@ __global__ void k_adj_dp(int64_t n, const SceneDev *__restrict__ sc,
                          const float4 *__restrict__ dpb, float4 *__restrict__ zb,
                          float *__restrict__ lb)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    int64_t p;
+    uint32_t sub;
+    if (!group_of<L>(n, p, sub)) return;
     const uint32_t i = pslot[p];
     const SceneDev &S = sc[id_scene[id[i]]];
     const float h = S.h, h2 = S.h2, cg = S.c_grad, ir0 = S.inv_rho0;
@@ -171,7 +196,7 @@ __global__ void k_adj_dp(int64_t n, const SceneDev *__restrict__ sc,
     const float3 di = f3(dpb[i]);
     float lsum = 0.f;
     float3 acc = make_float3(0.f, 0.f, 0.f);
-    for (uint32_t q = 0; q < cnt; ++q) {
+    for (uint32_t q = sub; q < cnt; q += L) {
         const uint32_t j = nslot[(size_t)q * n + p];
         const float4 zj = zl[j];
         const float3 d = make_float3(zi.x - zj.x, zi.y - zj.y, zi.z - zj.z);
@@ -188,6 +213,11 @@ __global__ void k_adj_dp(int64_t n, const SceneDev *__restrict__ sc,
         acc.y += s * hu.y;
         acc.z += s * hu.z;
     }
+    lsum = group_sum<L>(lsum);
+    acc.x = group_sum<L>(acc.x);
+    acc.y = group_sum<L>(acc.y);
+    acc.z = group_sum<L>(acc.z);
+    if (sub) return;
     lb[i] += ir0 * lsum;
     float4 b = zb[i];
     b.x += ir0 * acc.x;
@@ -197,6 +227,7 @@ __global__ void k_adj_dp(int64_t n, const SceneDev *__restrict__ sc,
 }
 
 // (c): constraint adjoints of the active particles (G, Cb in gc; Sb in sb)
+template <int L>
 __global__ void k_adj_lambda(int k, int64_t n, const SceneDev *__restrict__ sc,
                              const uint32_t *__restrict__ id_scene, const uint32_t *__restrict__ id,
                              const uint32_t *__restrict__ pslot, const uint32_t *__restrict__ pmeta,
@@ -204,13 +235,16 @@ __global__ void k_adj_lambda(int k, int64_t n, const SceneDev *__restrict__ sc,
                              float *__restrict__ lb, float4 *__restrict__ gc,
                              float *__restrict__ sb)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    int64_t p;
+    uint32_t sub;
+    if (!group_of<L>(n, p, sub)) return;
     const uint32_t i = pslot[p];
     const uint32_t meta = pmeta[p];
     if ((int)level_of(meta) <= k) {
-        gc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        sb[i] = 0.f;
+        if (sub == 0) {
+            gc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sb[i] = 0.f;
+        }
         return;
     }
     const SceneDev &S = sc[id_scene[id[i]]];
@@ -218,7 +252,7 @@ __global__ void k_adj_lambda(int k, int64_t n, const SceneDev *__restrict__ sc,
     const uint32_t cnt = meta & kMetaCount;
     const float4 zi = zl[i];
     float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
-    for (uint32_t q = 0; q < cnt; ++q) {
+    for (uint32_t q = sub; q < cnt; q += L) {
         const float4 zj = zl[nslot[(size_t)q * n + p]];
         const float dx = zi.x - zj.x, dy = zi.y - zj.y, dz = zi.z - zj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -231,6 +265,11 @@ __global__ void k_adj_lambda(int k, int64_t n, const SceneDev *__restrict__ sc,
             g2 += f * f * r2;
         }
     }
+    gx = group_sum<L>(gx);
+    gy = group_sum<L>(gy);
+    gz = group_sum<L>(gz);
+    g2 = group_sum<L>(g2);
+    if (sub) return;
     const float denom = S.c_s * (gx * gx + gy * gy + gz * gz + g2) + S.eps;
     const float l = lb[i];
     gc[i] = make_float4(gx, gy, gz, -l / denom);
@@ -239,6 +278,7 @@ __global__ void k_adj_lambda(int k, int64_t n, const SceneDev *__restrict__ sc,
 }
 
 // (d): position adjoints from the constraints C and S
+template <int L>
 __global__ void k_adj_constraint(int64_t n, const SceneDev *__restrict__ sc,
                                  const uint32_t *__restrict__ id_scene,
                                  const uint32_t *__restrict__ id, const uint32_t *__restrict__ pslot,
@@ -247,8 +287,9 @@ __global__ void k_adj_constraint(int64_t n, const SceneDev *__restrict__ sc,
                                  const float4 *__restrict__ gc, const float *__restrict__ sb,
                                  float4 *__restrict__ zb)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    int64_t p;
+    uint32_t sub;
+    if (!group_of<L>(n, p, sub)) return;
     const uint32_t i = pslot[p];
     const SceneDev &S = sc[id_scene[id[i]]];
     const float h = S.h, h2 = S.h2, cg = S.c_grad, c6 = 6.f * S.c_rho, c2 = 2.f * S.c_s;
@@ -257,7 +298,7 @@ __global__ void k_adj_constraint(int64_t n, const SceneDev *__restrict__ sc,
     const float4 gi = gc[i];
     const float si = sb[i];
     float3 acc = make_float3(0.f, 0.f, 0.f);
-    for (uint32_t q = 0; q < cnt; ++q) {
+    for (uint32_t q = sub; q < cnt; q += L) {
         const uint32_t j = nslot[(size_t)q * n + p];
         const float4 zj = zl[j];
         const float3 d = make_float3(zi.x - zj.x, zi.y - zj.y, zi.z - zj.z);
@@ -283,6 +324,10 @@ __global__ void k_adj_constraint(int64_t n, const SceneDev *__restrict__ sc,
             acc.z += c2 * hv.z;
         }
     }
+    acc.x = group_sum<L>(acc.x);
+    acc.y = group_sum<L>(acc.y);
+    acc.z = group_sum<L>(acc.z);
+    if (sub) return;
     float4 b = zb[i];
     b.x += acc.x;
     b.y += acc.y;
@@ -352,13 +397,14 @@ hipError_t enqueue_adjoint_step(const StepBuffers &b, const StepRecord &r, const
     const int64_t n = b.n;
     if (n == 0) return hipSuccess;
     const int K = b.n_iters;
-    // per-particle kernels: one wave per workgroup below 2^18 particles, so
-    // that a small rollout still spreads over every CU
-    const int tb = n >= (int64_t(1) << 18) ? 256 : 64;
+    const int tb = 256;
     const unsigned gb = blocks(n, tb);
+    // lanes per particle of the gather kernels: enough for about 2^19 threads
+    const int lanes = n >= (int64_t(1) << 19) ? 1 : n >= (int64_t(1) << 18) ? 2 : n >= (int64_t(1) << 17) ? 4 : 8;
+    const unsigned gl = blocks(n * lanes, tb);
     hipLaunchKernelGGL(k_adj_decode, dim3(b.n_tiles * tile_split(b.n_tiles)), dim3(kNbrThreads), 0,
                        s, b.n_tiles, r.tile_order, r.tile_ge, r.tile_start, r.tile_count,
-                       r.tile_rows, n, r.nbr, r.pmeta, w.nslot);
+                       r.tile_rows, n, (uint32_t)(b.nbr_cap + 7) / 8, r.nbr, r.pmeta, w.nslot);
     ACHK(hipGetLastError());
     hipLaunchKernelGGL(k_adj_commit, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene, r.id,
                        ax_in, av_in, w.zb, w.xb, w.lb);
@@ -367,15 +413,21 @@ hipError_t enqueue_adjoint_step(const StepBuffers &b, const StepRecord &r, const
         hipLaunchKernelGGL(k_adj_clamp, dim3(gb), dim3(tb), 0, s, k, n, b.scenes, b.id_scene,
                            r.id, r.lvl, r.snap[k + 1], w.zb, w.dpb);
         ACHK(hipGetLastError());
-        hipLaunchKernelGGL(k_adj_dp, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene, r.id,
-                           r.pslot, r.pmeta, w.nslot, r.snap[k], w.dpb, w.zb, w.lb);
-        ACHK(hipGetLastError());
-        hipLaunchKernelGGL(k_adj_lambda, dim3(gb), dim3(tb), 0, s, k, n, b.scenes, b.id_scene,
-                           r.id, r.pslot, r.pmeta, w.nslot, r.snap[k], w.lb, w.gc, w.sb);
-        ACHK(hipGetLastError());
-        hipLaunchKernelGGL(k_adj_constraint, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene,
-                           r.id, r.pslot, r.pmeta, w.nslot, r.snap[k], w.gc, w.sb, w.zb);
-        ACHK(hipGetLastError());
+#define GATHER(KERNEL, ...)                                                                      \
+    switch (lanes) {                                                                             \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(gl), dim3(tb), 0, s, __VA_ARGS__); break;          \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(gl), dim3(tb), 0, s, __VA_ARGS__); break;          \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(gl), dim3(tb), 0, s, __VA_ARGS__); break;          \
+    default: hipLaunchKernelGGL(KERNEL<8>, dim3(gl), dim3(tb), 0, s, __VA_ARGS__); break;         \
+    }                                                                                            \
+    ACHK(hipGetLastError())
+        GATHER(k_adj_dp, n, b.scenes, b.id_scene, r.id, r.pslot, r.pmeta, w.nslot, r.snap[k], w.dpb,
+               w.zb, w.lb);
+        GATHER(k_adj_lambda, k, n, b.scenes, b.id_scene, r.id, r.pslot, r.pmeta, w.nslot, r.snap[k],
+               w.lb, w.gc, w.sb);
+        GATHER(k_adj_constraint, n, b.scenes, b.id_scene, r.id, r.pslot, r.pmeta, w.nslot,
+               r.snap[k], w.gc, w.sb, w.zb);
+#undef GATHER
     }
     hipLaunchKernelGGL(k_adj_predict, dim3(gb), dim3(tb), 0, s, n, b.scenes, b.id_scene, r.id,
                        r.snap[0], w.zb, w.xb, ax_out, av_out);
