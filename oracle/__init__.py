@@ -60,7 +60,20 @@ class Trace(ctypes.Structure):
                 ("nbr_ids", ctypes.POINTER(ctypes.c_int32)),
                 ("nbr_cap", ctypes.c_int64), ("nbr_total", ctypes.c_int64),
                 ("xs_iter", ctypes.POINTER(ctypes.c_double)),
-                ("lambda_iter", ctypes.POINTER(ctypes.c_double))]
+                ("lambda_iter", ctypes.POINTER(ctypes.c_double)),
+                ("contacts", ctypes.POINTER(ctypes.c_uint8))]
+
+
+MAX_OBSTACLES = 4
+
+
+class Obstacle(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c", ctypes.c_double * 3), ("a", ctypes.c_double * 3)]
+
+
+class Contacts(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("ob", Obstacle * MAX_OBSTACLES),
+                ("stab_iters", ctypes.c_int32), ("stab_s", ctypes.c_int32)]
 
 
 _lib = None
@@ -78,6 +91,13 @@ def lib():
                                      ctypes.POINTER(ctypes.c_double)]
         L.orc_apbf_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod),
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Trace)]
+        L.orc_apbf_step_contacts.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod),
+                                             ctypes.POINTER(Contacts), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.POINTER(Trace)]
+        L.orc_obstacle_project.argtypes = [ctypes.POINTER(Obstacle), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
+        L.orc_contact_found.argtypes = [ctypes.POINTER(Obstacle), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_double]
         L.orc_pbf_step.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p]
         L.orc_density.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
@@ -158,6 +178,46 @@ class _LodHolder:
         self.lod.splat = float(getattr(scene, "splat", 0.0))
 
 
+def _obstacle(kind, centre, a) -> Obstacle:
+    o = Obstacle()
+    o.kind = int(kind)
+    for d in range(3):
+        o.c[d] = float(centre[d])
+        o.a[d] = float(a[d])
+    return o
+
+
+def contacts(scene):
+    """The scene's obstacles and pre-stabilisation settings, or None."""
+    obs = getattr(scene, "obstacles", ())
+    if not obs and not getattr(scene, "stab_iters", 0):
+        return None
+    oc = Contacts()
+    oc.count = len(obs)
+    for k, (kind, centre, a) in enumerate(obs):
+        oc.ob[k] = _obstacle(kind, centre, a)
+    oc.stab_iters = int(scene.stab_iters)
+    oc.stab_s = int(scene.stab_s)
+    return oc
+
+
+def obstacle_project(kind, centre, a, x):
+    """Closest surface point of a solid obstacle to x if x is inside it,
+    else None (float64)."""
+    o = _obstacle(kind, centre, a)
+    x = np.ascontiguousarray(x, np.float64).reshape(3)
+    y = np.zeros(3, np.float64)
+    inside = lib().orc_obstacle_project(ctypes.byref(o), _ptr(x, ctypes.c_double),
+                                        _ptr(y, ctypes.c_double))
+    return y if inside else None
+
+
+def contact_found(kind, centre, a, x, margin) -> bool:
+    o = _obstacle(kind, centre, a)
+    x = np.ascontiguousarray(x, np.float64).reshape(3)
+    return bool(lib().orc_contact_found(ctypes.byref(o), _ptr(x, ctypes.c_double), float(margin)))
+
+
 def levels(scene, x) -> np.ndarray:
     p = params(scene)
     hold = _LodHolder(scene)
@@ -177,6 +237,8 @@ def apbf_step(scene, x, v, trace=False, mode=None, levels=None, n_min=None, n_ma
     after every lambda pass."""
     p = params(scene, n_min=n_min, n_max=n_max)
     hold = _LodHolder(scene, mode, levels)
+    oc = contacts(scene)
+    ocp = ctypes.byref(oc) if oc is not None else None
     x = np.array(x, np.float64, order="C").reshape(-1, 3)
     v = np.array(v, np.float64, order="C").reshape(-1, 3)
     n, K = p.n, p.n_max
@@ -188,6 +250,7 @@ def apbf_step(scene, x, v, trace=False, mode=None, levels=None, n_min=None, n_ma
             "perm": np.zeros(n, np.int32), "nbr_count": np.zeros(n, np.int32),
             "xs_iter": np.zeros((K + 1, n, 3), np.float64),
             "lambda_iter": np.zeros((K, n), np.float64),
+            "contacts": np.zeros(n, np.uint8),
         }
         tr = Trace()
         tr.levels = _ptr(info["levels"], ctypes.c_int32)
@@ -196,19 +259,20 @@ def apbf_step(scene, x, v, trace=False, mode=None, levels=None, n_min=None, n_ma
         tr.nbr_count = _ptr(info["nbr_count"], ctypes.c_int32)
         tr.xs_iter = _ptr(info["xs_iter"], ctypes.c_double)
         tr.lambda_iter = _ptr(info["lambda_iter"], ctypes.c_double)
+        tr.contacts = _ptr(info["contacts"], ctypes.c_uint8)
         # first call sizes the neighbour list, second call fills it
         x0, v0 = x.copy(), v.copy()
         tr.nbr_cap = 0
-        rc = lib().orc_apbf_step(ctypes.byref(p), ctypes.byref(hold.lod), x0.ctypes.data,
-                                 v0.ctypes.data, ctypes.byref(tr))
+        rc = lib().orc_apbf_step_contacts(ctypes.byref(p), ctypes.byref(hold.lod), ocp,
+                                          x0.ctypes.data, v0.ctypes.data, ctypes.byref(tr))
         if rc != ORC_OK:
             raise ValueError(f"orc_apbf_step failed ({rc})")
         ids = np.zeros(max(int(tr.nbr_total), 1), np.int32)
         info["nbr_ids"] = ids[: int(tr.nbr_total)]
         tr.nbr_ids = _ptr(ids, ctypes.c_int32)
         tr.nbr_cap = ids.size
-    rc = lib().orc_apbf_step(ctypes.byref(p), ctypes.byref(hold.lod), x.ctypes.data,
-                             v.ctypes.data, ctypes.byref(tr) if tr is not None else None)
+    rc = lib().orc_apbf_step_contacts(ctypes.byref(p), ctypes.byref(hold.lod), ocp, x.ctypes.data,
+                                      v.ctypes.data, ctypes.byref(tr) if tr is not None else None)
     if rc != ORC_OK:
         raise ValueError(f"orc_apbf_step failed ({rc})")
     if trace:

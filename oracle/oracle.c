@@ -29,7 +29,17 @@
  *   - A finished particle keeps its position and its last lambda; active
  *     particles use that lambda in their corrections (Fig. 5).
  *   - Contacts are the box walls: positions are clamped to [lo, hi] after
- *     prediction and after each update.  No pre-stabilisation iterations.
+ *     prediction and after each update.  Optional solid obstacles (sphere,
+ *     cone with a vertical axis, axis-aligned box; signed-distance shapes,
+ *     Section 6) add the contacts of Fig. 7: contact finding once per step
+ *     from the predicted positions (the obstacles whose bounding volume,
+ *     grown by h, holds x*, decided in float32 like the kernel), then
+ *     pre-stabilisation (Section 4.3, Fig. 6) of the particles with
+ *     N_i < S: each iteration moves x* of a particle found inside an
+ *     obstacle to the closest point of its surface (clamped into the box)
+ *     and moves x by the same amount; finally, in every update of an active
+ *     particle, x* + Delta p is moved out of each found obstacle it lies
+ *     in, before the wall clamp.
  *   - Iterations k = 0 .. n_max-1 (the paper's l = k + 1); particle i is
  *     active while k < N_i.
  *   - Grid cells have edge h from lo, keys are x-fastest, coordinates are
@@ -88,7 +98,26 @@ typedef struct {
     int64_t nbr_total;      /* out: total entries (written even when nbr_ids is too small) */
     double *xs_iter;        /* [(n_max+1)*n*3] x* before iteration 0 and after each */
     double *lambda_iter;    /* [n_max*n] lambda after the lambda pass of each iteration */
+    uint8_t *contacts;      /* [n]  obstacles found for each particle (bit o = obstacle o) */
 } orc_trace;
+
+/* Solid obstacles and the pre-stabilisation set (Section 4.3, Fig. 7). */
+enum { ORC_MAX_OBST = 4 };
+enum { ORC_OB_SPHERE = 1, ORC_OB_CONE = 2, ORC_OB_BOX = 3 };
+
+typedef struct {
+    int32_t kind;  /* ORC_OB_* */
+    double c[3];   /* sphere: centre; cone: centre of the base disc; box: centre */
+    double a[3];   /* sphere: a[0] radius; cone: a[0] base radius, a[1] height
+                      (apex above the base, +y); box: half extents */
+} orc_obstacle;
+
+typedef struct {
+    int32_t count;                   /* 0 .. ORC_MAX_OBST */
+    orc_obstacle ob[ORC_MAX_OBST];
+    int32_t stab_iters;              /* pre-stabilisation iterations */
+    int32_t stab_s;                  /* S: particles with N_i < S are pre-stabilised */
+} orc_contacts;
 
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_MEM = -3 };
 
@@ -297,6 +326,117 @@ static void clamp_box(const orc_params *p, double *x)
 }
 
 /* ------------------------------------------------------------------ */
+/* obstacles (contact lines of Fig. 7)                                 */
+/* ------------------------------------------------------------------ */
+
+/* Contact finding (Fig. 7, second loop): obstacle o is a contact of a
+ * particle when its bounding volume grown by the margin holds x*.  Decided
+ * in float32 with one rounding per operation, like the kernel. */
+int orc_contact_found(const orc_obstacle *o, const double *x, double margin_d)
+{
+    const float m = (float)margin_d;
+    const float dx = (float)x[0] - (float)o->c[0];
+    const float dy = (float)x[1] - (float)o->c[1];
+    const float dz = (float)x[2] - (float)o->c[2];
+    const float a0 = (float)o->a[0], a1 = (float)o->a[1], a2 = (float)o->a[2];
+    if (o->kind == ORC_OB_SPHERE) {
+        const float r = a0 + m;
+        return dx * dx + dy * dy + dz * dz < r * r;
+    }
+    if (o->kind == ORC_OB_CONE) {
+        const float r = a0 + m;
+        return dy > -m && dy < a1 + m && dx * dx + dz * dz < r * r;
+    }
+    if (o->kind == ORC_OB_BOX)
+        return fabsf(dx) < a0 + m && fabsf(dy) < a1 + m && fabsf(dz) < a2 + m;
+    return 0;
+}
+
+/* If x lies inside the solid obstacle, write the closest point of the
+ * obstacle's surface to y and return 1 (the contact constraint's
+ * projection: the signed distance becomes zero); otherwise return 0.
+ *   sphere: radially out from the centre (straight up from the centre
+ *     itself);
+ *   box: through the face of least penetration (first axis on ties);
+ *   cone (the solid of revolution of the right triangle with legs R along
+ *     the base and H along the axis): in the plane of the axis and x, to
+ *     the foot of the perpendicular on the slant edge or straight down to
+ *     the base, whichever is nearer (the base on ties); on the axis the
+ *     plane is taken through +x. */
+int orc_obstacle_project(const orc_obstacle *o, const double *x, double *y)
+{
+    const double d0 = x[0] - o->c[0], d1 = x[1] - o->c[1], d2 = x[2] - o->c[2];
+    if (o->kind == ORC_OB_SPHERE) {
+        const double R = o->a[0];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (!(r2 < R * R)) return 0;
+        const double r = sqrt(r2);
+        if (r > 0.0) {
+            y[0] = o->c[0] + R * d0 / r;
+            y[1] = o->c[1] + R * d1 / r;
+            y[2] = o->c[2] + R * d2 / r;
+        } else {
+            y[0] = o->c[0];
+            y[1] = o->c[1] + R;
+            y[2] = o->c[2];
+        }
+        return 1;
+    }
+    if (o->kind == ORC_OB_CONE) {
+        const double R = o->a[0], H = o->a[1];
+        double rho = sqrt(d0 * d0 + d2 * d2), yb = d1;
+        if (!(yb > 0.0 && rho * H + yb * R < H * R)) return 0;
+        const double L = sqrt(H * H + R * R);
+        const double ds = (H * R - rho * H - yb * R) / L;  /* distance to the slant line */
+        const double ux = rho > 0.0 ? d0 / rho : 1.0, uz = rho > 0.0 ? d2 / rho : 0.0;
+        if (ds < yb) {
+            rho += ds * H / L;
+            yb += ds * R / L;
+        } else {
+            yb = 0.0;
+        }
+        y[0] = o->c[0] + rho * ux;
+        y[1] = o->c[1] + yb;
+        y[2] = o->c[2] + rho * uz;
+        return 1;
+    }
+    if (o->kind == ORC_OB_BOX) {
+        const double d[3] = {d0, d1, d2};
+        double q[3];
+        for (int a = 0; a < 3; ++a) {
+            q[a] = fabs(d[a]) - o->a[a];
+            if (!(q[a] < 0.0)) return 0;
+        }
+        int m = 0;
+        for (int a = 1; a < 3; ++a)
+            if (q[a] > q[m]) m = a;
+        y[0] = x[0];
+        y[1] = x[1];
+        y[2] = x[2];
+        y[m] = o->c[m] + (d[m] >= 0.0 ? o->a[m] : -o->a[m]);
+        return 1;
+    }
+    return 0;
+}
+
+/* Contact response of an active particle's update: x* + Delta p is moved
+ * out of every found obstacle it lies in, in obstacle order, then clamped
+ * to the walls. */
+static void contact_response(const orc_params *p, const orc_contacts *oc, uint32_t mask, double *x)
+{
+    if (oc)
+        for (int o = 0; o < oc->count; ++o) {
+            double y[3];
+            if ((mask >> o) & 1u && orc_obstacle_project(&oc->ob[o], x, y)) {
+                x[0] = y[0];
+                x[1] = y[1];
+                x[2] = y[2];
+            }
+        }
+    clamp_box(p, x);
+}
+
+/* ------------------------------------------------------------------ */
 /* levels (Eq. 8, adaption model of Section 4.1)                       */
 /* ------------------------------------------------------------------ */
 
@@ -479,12 +619,38 @@ static void copy_trace_neighbours(const orc_params *p, orc_trace *tr, const int6
 /* one APBF step (Fig. 7)                                              */
 /* ------------------------------------------------------------------ */
 
+static int check_contacts(const orc_params *p, const orc_contacts *oc)
+{
+    if (!oc) return ORC_OK;
+    if (oc->count < 0 || oc->count > ORC_MAX_OBST || oc->stab_iters < 0 || oc->stab_s < 1 ||
+        oc->stab_s > p->n_max)
+        return ORC_ERR_ARG;
+    for (int o = 0; o < oc->count; ++o) {
+        const orc_obstacle *b = &oc->ob[o];
+        if (b->kind < ORC_OB_SPHERE || b->kind > ORC_OB_BOX || !(b->a[0] > 0)) return ORC_ERR_ARG;
+        if (b->kind != ORC_OB_SPHERE && !(b->a[1] > 0)) return ORC_ERR_ARG;
+        if (b->kind == ORC_OB_BOX && !(b->a[2] > 0)) return ORC_ERR_ARG;
+    }
+    return ORC_OK;
+}
+
+int orc_apbf_step_contacts(const orc_params *p, const orc_lod *lod, const orc_contacts *oc,
+                           double *x, double *v, orc_trace *tr);
+
 /* x, v: n*3 doubles in particle-ID order, advanced in place by one step.
  * tr may be NULL; any of its pointers may be NULL. */
 int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v, orc_trace *tr)
 {
+    return orc_apbf_step_contacts(p, lod, NULL, x, v, tr);
+}
+
+/* The same step with solid obstacles (oc may be NULL: walls only). */
+int orc_apbf_step_contacts(const orc_params *p, const orc_lod *lod, const orc_contacts *oc,
+                           double *x, double *v, orc_trace *tr)
+{
     int rc = check_params(p);
     if (rc) return rc;
+    if ((rc = check_contacts(p, oc))) return rc;
     const int32_t n = p->n;
     const int32_t K = p->n_max;
     size_t n3 = (size_t)n * 3;
@@ -494,9 +660,10 @@ int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v,
     double *lam = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
     uint32_t *keys = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
     int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    uint8_t *cmask = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
     int64_t *off = NULL;
     int32_t *ids = NULL;
-    if (!lev || !xs || !dp || !lam || !keys || !perm) { rc = ORC_ERR_MEM; goto done; }
+    if (!lev || !xs || !dp || !lam || !keys || !perm || !cmask) { rc = ORC_ERR_MEM; goto done; }
 
     /* levels from the positions at the start of the step */
     rc = orc_levels(p, lod, x, lev);
@@ -505,7 +672,31 @@ int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v,
     rc = predict_and_neighbours(p, x, v, xs, keys, perm, &off, &ids);
     if (rc) goto done;
 
+    if (oc && oc->count > 0) {
+        /* contact finding from the predicted positions */
+        for (int32_t i = 0; i < n; ++i)
+            for (int o = 0; o < oc->count; ++o)
+                if (orc_contact_found(&oc->ob[o], xs + 3 * (int64_t)i, p->h)) cmask[i] |= (uint8_t)(1u << o);
+        /* pre-stabilisation of the particles with N_i < S: x* to the
+         * obstacle's surface, x moved along (no velocity is gained) */
+        for (int32_t it = 0; it < oc->stab_iters; ++it)
+            for (int32_t i = 0; i < n; ++i) {
+                if (!(lev[i] < oc->stab_s)) continue;
+                double *xi = x + 3 * (int64_t)i, *si = xs + 3 * (int64_t)i;
+                for (int o = 0; o < oc->count; ++o) {
+                    double y[3];
+                    if (!((cmask[i] >> o) & 1u) || !orc_obstacle_project(&oc->ob[o], si, y)) continue;
+                    clamp_box(p, y);
+                    for (int d = 0; d < 3; ++d) {
+                        xi[d] += y[d] - si[d];
+                        si[d] = y[d];
+                    }
+                }
+            }
+    }
+
     if (tr) {
+        if (tr->contacts) memcpy(tr->contacts, cmask, (size_t)n);
         if (tr->levels) memcpy(tr->levels, lev, sizeof(int32_t) * (size_t)n);
         if (tr->keys) memcpy(tr->keys, keys, sizeof(uint32_t) * (size_t)n);
         if (tr->perm) memcpy(tr->perm, perm, sizeof(int32_t) * (size_t)n);
@@ -525,7 +716,7 @@ int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v,
         for (int32_t i = 0; i < n; ++i)
             if (lev[i] > k) {
                 for (int d = 0; d < 3; ++d) xs[3 * (int64_t)i + d] += dp[3 * (int64_t)i + d];
-                clamp_box(p, xs + 3 * (int64_t)i);
+                contact_response(p, oc, cmask[i], xs + 3 * (int64_t)i);
             }
         if (tr && tr->lambda_iter) memcpy(tr->lambda_iter + (size_t)k * n, lam, sizeof(double) * (size_t)n);
         if (tr && tr->xs_iter) memcpy(tr->xs_iter + (size_t)(k + 1) * n3, xs, sizeof(double) * n3);
@@ -537,7 +728,7 @@ int orc_apbf_step(const orc_params *p, const orc_lod *lod, double *x, double *v,
         x[e] = xs[e];
     }
 done:
-    free(lev); free(xs); free(dp); free(lam); free(keys); free(perm); free(off); free(ids);
+    free(lev); free(xs); free(dp); free(lam); free(keys); free(perm); free(cmask); free(off); free(ids);
     return rc;
 }
 

@@ -46,6 +46,13 @@ LOD_EXPLICIT = 1
 LOD_DTC = 2
 LOD_DTVS = 3
 
+#: solid obstacle kinds: (kind, centre, a) with a = (radius, 0, 0) for a
+#: sphere, (base radius, height, 0) for a cone standing on its base disc
+#: (centre = centre of the base, apex up), half extents for a box
+OB_SPHERE = 1
+OB_CONE = 2
+OB_BOX = 3
+
 
 @dataclasses.dataclass
 class Scene:
@@ -90,6 +97,12 @@ class Scene:
     splat: float = F32(SPACING / 2)
     steps: int = 1
     target: Optional[np.ndarray] = None
+    # solid obstacles ((kind, centre, a) tuples, float32 values) and
+    # pre-stabilisation: stab_iters iterations for the particles with
+    # level < stab_s
+    obstacles: tuple = ()
+    stab_iters: int = 0
+    stab_s: int = 1
 
     def __post_init__(self):
         self.x0 = np.ascontiguousarray(self.x0, dtype=F32).reshape(-1, 3)
@@ -110,6 +123,8 @@ class Scene:
         self.dims = np.asarray(self.dims, dtype=np.int32).reshape(3)
         if self.levels is not None:
             self.levels = np.ascontiguousarray(self.levels, dtype=np.uint8)
+        self.obstacles = tuple((int(k), tuple(F32(v) for v in c), tuple(F32(v) for v in a))
+                               for k, c, a in self.obstacles)
 
     @property
     def n(self) -> int:
@@ -274,6 +289,32 @@ def dam_break_batch(seed: int = 4, n_scenes: int = 64,
                          lod_mode=LOD_DTC, camera=cam, d_near=dn, d_far=df,
                          steps=100, dt=DT_DEEP))
     return out
+
+
+def multi_dam_break(seed: int = 6, a: int = 35, ny: int = 46, box=(6.4, 3.2, 6.4),
+                    cone=(1.2, 2.0), n_min: int = 4, n_max: int = 8, stab_iters: int = 1,
+                    stab_s: int = 6, steps: int = 100) -> Scene:
+    """Four dam-break blocks of a x ny x a lattice points in the corners of a
+    box, around a solid cone standing on the floor at the box centre (base
+    radius, height = ``cone``): the multi-dam-break scene of Section 7.3
+    (4 x 56,350 = 225,400 particles at the defaults).  Distance-to-camera
+    levels N_i in {n_min..n_max}, camera above the front edge; particles
+    with N_i < stab_s get stab_iters pre-stabilisation iterations; dt =
+    1/120, v = 0.
+    """
+    rng = np.random.default_rng(seed)
+    X, Y, Z = (float(v) for v in box)
+    w = a * SPACING
+    blocks = [lattice(a, ny, a, (ox, 0.0, oz)) for oz in (0.0, Z - w) for ox in (0.0, X - w)]
+    x = _jitter(rng, np.concatenate(blocks))
+    cam = (X / 2.0, 2.0 * Y, -Z / 2.0)
+    x32 = x.astype(F32)
+    dn, df = _camera_range(x32, cam)
+    obst = ((OB_CONE, (X / 2.0, 0.0, Z / 2.0), (cone[0], cone[1], 0.0)),)
+    return Scene(name="multi_dam_break", x0=x32, v0=np.zeros_like(x32), lo=(0, 0, 0),
+                 hi=box, n_min=n_min, n_max=n_max, lod_mode=LOD_DTC, camera=cam,
+                 d_near=dn, d_far=df, steps=steps, dt=DT_DEEP, obstacles=obst,
+                 stab_iters=stab_iters, stab_s=stab_s)
 
 
 def rollout_32k(seed: int = 5) -> Scene:
