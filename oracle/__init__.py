@@ -82,8 +82,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not _LIB_PATH.exists():
-            build(force=True)
+        build(force=False)  # rebuilds when oracle.c is newer than the library
         L = ctypes.CDLL(str(_LIB_PATH))
         L.orc_poly6.restype = ctypes.c_double
         L.orc_poly6.argtypes = [ctypes.c_double, ctypes.c_double]

@@ -30,10 +30,10 @@
  *     particles use that lambda in their corrections (Fig. 5).
  *   - Contacts are the box walls: positions are clamped to [lo, hi] after
  *     prediction and after each update.  Optional solid obstacles (sphere,
- *     cone with a vertical axis, axis-aligned box; signed-distance shapes,
- *     Section 6) add the contacts of Fig. 7: contact finding once per step
- *     from the predicted positions (the obstacles whose bounding volume,
- *     grown by h, holds x*, decided in float32 like the kernel), then
+ *     cone with a vertical axis standing on the floor, axis-aligned box;
+ *     signed-distance shapes, Section 6) add the contacts of Fig. 7: contact
+ *     finding once per step from the predicted positions (the obstacles
+ *     that, grown by h, hold x*, decided in float32 like the kernel), then
  *     pre-stabilisation (Section 4.3, Fig. 6) of the particles with
  *     N_i < S: each iteration moves x* of a particle found inside an
  *     obstacle to the closest point of its surface (clamped into the box)
@@ -96,7 +96,8 @@ typedef struct {
     int32_t *nbr_ids;       /* [nbr_cap] neighbour IDs, particle by particle, ascending */
     int64_t nbr_cap;
     int64_t nbr_total;      /* out: total entries (written even when nbr_ids is too small) */
-    double *xs_iter;        /* [(n_max+1)*n*3] x* before iteration 0 and after each */
+    double *xs_iter;        /* [(n_max+1)*n*3] x* after prediction (the keys and neighbours
+                               come from it; pre-stabilisation follows) and after each iteration */
     double *lambda_iter;    /* [n_max*n] lambda after the lambda pass of each iteration */
     uint8_t *contacts;      /* [n]  obstacles found for each particle (bit o = obstacle o) */
 } orc_trace;
@@ -107,9 +108,10 @@ enum { ORC_OB_SPHERE = 1, ORC_OB_CONE = 2, ORC_OB_BOX = 3 };
 
 typedef struct {
     int32_t kind;  /* ORC_OB_* */
-    double c[3];   /* sphere: centre; cone: centre of the base disc; box: centre */
+    double c[3];   /* sphere: centre; cone: centre of the base circle; box: centre */
     double a[3];   /* sphere: a[0] radius; cone: a[0] base radius, a[1] height
-                      (apex above the base, +y); box: half extents */
+                      (apex above the base, +y; the slant continues below the
+                      base); box: half extents */
 } orc_obstacle;
 
 typedef struct {
@@ -330,8 +332,10 @@ static void clamp_box(const orc_params *p, double *x)
 /* ------------------------------------------------------------------ */
 
 /* Contact finding (Fig. 7, second loop): obstacle o is a contact of a
- * particle when its bounding volume grown by the margin holds x*.  Decided
- * in float32 with one rounding per operation, like the kernel. */
+ * particle when the obstacle grown by the margin holds x* (sphere: radius
+ * + m; box: half extents + m; cone: its slant moved out by m; for the box
+ * this is its bounding box grown by m, a superset of the points within m).
+ * Decided in float32 with one rounding per operation, like the kernel. */
 int orc_contact_found(const orc_obstacle *o, const double *x, double margin_d)
 {
     const float m = (float)margin_d;
@@ -344,8 +348,10 @@ int orc_contact_found(const orc_obstacle *o, const double *x, double margin_d)
         return dx * dx + dy * dy + dz * dz < r * r;
     }
     if (o->kind == ORC_OB_CONE) {
-        const float r = a0 + m;
-        return dy > -m && dy < a1 + m && dx * dx + dz * dz < r * r;
+        /* the cone grown by m: its slant moved out by m along the normal */
+        const float rho = sqrtf(dx * dx + dz * dz);
+        const float L = sqrtf(a1 * a1 + a0 * a0);
+        return rho * a1 + dy * a0 < a1 * a0 + m * L;
     }
     if (o->kind == ORC_OB_BOX)
         return fabsf(dx) < a0 + m && fabsf(dy) < a1 + m && fabsf(dz) < a2 + m;
@@ -358,11 +364,11 @@ int orc_contact_found(const orc_obstacle *o, const double *x, double margin_d)
  *   sphere: radially out from the centre (straight up from the centre
  *     itself);
  *   box: through the face of least penetration (first axis on ties);
- *   cone (the solid of revolution of the right triangle with legs R along
- *     the base and H along the axis): in the plane of the axis and x, to
- *     the foot of the perpendicular on the slant edge or straight down to
- *     the base, whichever is nearer (the base on ties); on the axis the
- *     plane is taken through +x. */
+ *   cone (apex H above the centre c, radius R at the height of c, and its
+ *     slant continued below that circle: a cone standing on the floor, so
+ *     fluid pressed into it leaves through the slant, never under it): in
+ *     the plane of the axis and x, to the foot of the perpendicular on the
+ *     slant line; on the axis the plane is taken through +x. */
 int orc_obstacle_project(const orc_obstacle *o, const double *x, double *y)
 {
     const double d0 = x[0] - o->c[0], d1 = x[1] - o->c[1], d2 = x[2] - o->c[2];
@@ -385,16 +391,12 @@ int orc_obstacle_project(const orc_obstacle *o, const double *x, double *y)
     if (o->kind == ORC_OB_CONE) {
         const double R = o->a[0], H = o->a[1];
         double rho = sqrt(d0 * d0 + d2 * d2), yb = d1;
-        if (!(yb > 0.0 && rho * H + yb * R < H * R)) return 0;
+        if (!(rho * H + yb * R < H * R)) return 0;
         const double L = sqrt(H * H + R * R);
         const double ds = (H * R - rho * H - yb * R) / L;  /* distance to the slant line */
         const double ux = rho > 0.0 ? d0 / rho : 1.0, uz = rho > 0.0 ? d2 / rho : 0.0;
-        if (ds < yb) {
-            rho += ds * H / L;
-            yb += ds * R / L;
-        } else {
-            yb = 0.0;
-        }
+        rho += ds * H / L;
+        yb += ds * R / L;
         y[0] = o->c[0] + rho * ux;
         y[1] = o->c[1] + yb;
         y[2] = o->c[2] + rho * uz;
@@ -672,6 +674,14 @@ int orc_apbf_step_contacts(const orc_params *p, const orc_lod *lod, const orc_co
     rc = predict_and_neighbours(p, x, v, xs, keys, perm, &off, &ids);
     if (rc) goto done;
 
+    if (tr) {
+        if (tr->levels) memcpy(tr->levels, lev, sizeof(int32_t) * (size_t)n);
+        if (tr->keys) memcpy(tr->keys, keys, sizeof(uint32_t) * (size_t)n);
+        if (tr->perm) memcpy(tr->perm, perm, sizeof(int32_t) * (size_t)n);
+        copy_trace_neighbours(p, tr, off, ids);
+        if (tr->xs_iter) memcpy(tr->xs_iter, xs, sizeof(double) * n3);
+    }
+
     if (oc && oc->count > 0) {
         /* contact finding from the predicted positions */
         for (int32_t i = 0; i < n; ++i)
@@ -694,15 +704,7 @@ int orc_apbf_step_contacts(const orc_params *p, const orc_lod *lod, const orc_co
                 }
             }
     }
-
-    if (tr) {
-        if (tr->contacts) memcpy(tr->contacts, cmask, (size_t)n);
-        if (tr->levels) memcpy(tr->levels, lev, sizeof(int32_t) * (size_t)n);
-        if (tr->keys) memcpy(tr->keys, keys, sizeof(uint32_t) * (size_t)n);
-        if (tr->perm) memcpy(tr->perm, perm, sizeof(int32_t) * (size_t)n);
-        copy_trace_neighbours(p, tr, off, ids);
-        if (tr->xs_iter) memcpy(tr->xs_iter, xs, sizeof(double) * n3);
-    }
+    if (tr && tr->contacts) memcpy(tr->contacts, cmask, (size_t)n);
 
     /* solver iterations: particle i is active in iteration k while k < N_i */
     for (int32_t k = 0; k < K; ++k) {

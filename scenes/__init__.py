@@ -292,7 +292,7 @@ def dam_break_batch(seed: int = 4, n_scenes: int = 64,
 
 
 def multi_dam_break(seed: int = 6, a: int = 35, ny: int = 46, box=(6.4, 3.2, 6.4),
-                    cone=(1.2, 2.0), n_min: int = 4, n_max: int = 8, stab_iters: int = 1,
+                    cone=(1.5, 2.0), n_min: int = 4, n_max: int = 8, stab_iters: int = 1,
                     stab_s: int = 6, steps: int = 100) -> Scene:
     """Four dam-break blocks of a x ny x a lattice points in the corners of a
     box, around a solid cone standing on the floor at the box centre (base

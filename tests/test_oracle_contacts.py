@@ -50,19 +50,16 @@ def _box_surface(c, e, step=0.0025):
 
 
 def _cone_surface(c, R, H, step=0.004):
-    # slant: points at height t along the axis, radius R (1 - t/H); base: disc
+    # the slant, from the apex down to twice the base radius (the cone
+    # stands on the floor: its slant continues below the base circle)
     pts = []
     L = np.hypot(R, H)
-    for s in np.arange(0.0, L + step / 2, step):
-        r = R * (1 - s / L)
-        y = H * s / L
+    for s in np.arange(0.0, 2 * L + step / 2, step):
+        r = R * s / L
+        y = H * (1 - s / L)
         k = max(1, int(np.ceil(2 * np.pi * r / step)))
         ph = np.arange(k) * 2 * np.pi / k
         pts.append(np.stack([r * np.cos(ph), np.full(k, y), r * np.sin(ph)], -1))
-    for r in np.arange(0.0, R + step / 2, step):
-        k = max(1, int(np.ceil(2 * np.pi * r / step)))
-        ph = np.arange(k) * 2 * np.pi / k
-        pts.append(np.stack([r * np.cos(ph), np.zeros(k), r * np.sin(ph)], -1))
     return np.asarray(c) + np.concatenate(pts), step
 
 
@@ -74,9 +71,7 @@ def _on_surface(kind, c, a, y, tol=1e-12):
         q = np.abs(d) - np.asarray(a)
         return abs(q.max()) <= tol and np.all(q <= tol)
     rho = np.hypot(d[0], d[2])
-    on_base = abs(d[1]) <= tol and rho <= a[0] + tol
-    on_slant = abs(rho / a[0] + d[1] / a[1] - 1.0) <= tol and -tol <= d[1] <= a[1] + tol
-    return on_base or on_slant
+    return abs(rho / a[0] + d[1] / a[1] - 1.0) <= tol and d[1] <= a[1] + tol
 
 
 def _inside(kind, c, a, x):
@@ -85,7 +80,7 @@ def _inside(kind, c, a, x):
         return np.linalg.norm(d) < a[0]
     if kind == BOX:
         return bool(np.all(np.abs(d) < np.asarray(a)))
-    return d[1] > 0 and np.hypot(d[0], d[2]) / a[0] + d[1] / a[1] < 1.0
+    return np.hypot(d[0], d[2]) / a[0] + d[1] / a[1] < 1.0
 
 
 @pytest.mark.parametrize("kind,c,a,maker", [
@@ -98,8 +93,8 @@ def test_projection_is_the_closest_surface_point(kind, c, a, maker):
     rng = np.random.default_rng(kind)
     # points drawn around the obstacle; about half fall inside
     if kind == CONE:
-        lo = np.asarray(c) - (a[0], 0.0, a[0])
-        hi = np.asarray(c) + (a[0], a[1], a[0])
+        lo = np.asarray(c) - (1.3 * a[0], 0.3 * a[1], 1.3 * a[0])
+        hi = np.asarray(c) + (1.3 * a[0], a[1], 1.3 * a[0])
     else:
         ext = np.array(a if kind == BOX else (a[0],) * 3)
         lo, hi = np.asarray(c) - 1.1 * ext, np.asarray(c) + 1.1 * ext
@@ -128,8 +123,12 @@ def test_points_outside_are_not_moved():
                           (SPHERE, (0, 0, 0), (0.5, 0, 0), (0.0, 0.0, 0.6)),
                           (BOX, (0, 0, 0), (1, 2, 3), (1.0001, 0.0, 0.0)),
                           (CONE, (0, 0, 0), (1, 2, 0), (0.51, 1.0, 0.0)),
-                          (CONE, (0, 0, 0), (1, 2, 0), (0.1, -0.001, 0.0))]:
+                          (CONE, (0, 0, 0), (1, 2, 0), (1.11, -0.2, 0.0)),
+                          (CONE, (0, 0, 0), (1, 2, 0), (0.0, 2.001, 0.0))]:
         assert oracle.obstacle_project(kind, c, a, x) is None
+    # below the base circle the slant continues: a point there is inside
+    y = oracle.obstacle_project(CONE, (0, 0, 0), (1, 2, 0), (1.05, -0.2, 0.0))
+    assert y is not None and y[0] > 1.05
 
 
 def test_degenerate_projections():
@@ -145,15 +144,17 @@ def test_degenerate_projections():
 
 def test_contact_finding_margins():
     h = 0.1
-    # sphere: grown radius 1.1; box: half extents + h per axis; cone: a
-    # cylinder around it grown by h
+    # sphere: grown radius 1.1; box: half extents + h per axis; cone: the
+    # slant moved out by h (distance to the slant line below h)
     assert oracle.contact_found(SPHERE, (0, 0, 0), (1, 0, 0), (1.09, 0, 0), h)
     assert not oracle.contact_found(SPHERE, (0, 0, 0), (1, 0, 0), (1.11, 0, 0), h)
     assert oracle.contact_found(BOX, (0, 0, 0), (1, 1, 1), (1.09, 1.09, 1.09), h)
     assert not oracle.contact_found(BOX, (0, 0, 0), (1, 1, 1), (1.09, 1.11, 0), h)
-    assert oracle.contact_found(CONE, (0, 0, 0), (1, 2, 0), (1.05, 2.05, 0.0), h)
-    assert not oracle.contact_found(CONE, (0, 0, 0), (1, 2, 0), (0.0, 2.11, 0.0), h)
-    assert not oracle.contact_found(CONE, (0, 0, 0), (1, 2, 0), (0.0, -0.11, 0.0), h)
+    n = np.array([2.0, 1.0]) / np.sqrt(5.0)  # outward normal of the slant (rho, y)
+    on = np.array([0.5, 1.0])                 # a point of the slant line
+    for s, found in ((0.09, True), (0.11, False)):
+        rho, y = on + s * n
+        assert oracle.contact_found(CONE, (0, 0, 0), (1, 2, 0), (0.6 * rho, y, 0.8 * rho), h) == found
 
 
 def _single(x, v, obstacles, stab_iters=0, stab_s=1, levels=(1,), n_max=None):
