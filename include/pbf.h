@@ -26,7 +26,9 @@
  *     per step from the predicted positions and kept for every iteration;
  *   - a finished particle keeps its last lambda, and active neighbours use it;
  *   - contacts are the box walls: positions are clamped to [lo, hi] after
- *     prediction and after every update;
+ *     prediction and after every update; optional solid obstacles add the
+ *     contact finding, pre-stabilisation and contact response of Fig. 7
+ *     (pbf_batch_set_obstacles);
  *   - iteration k = 0..n_max-1 corrects particle i only while k < N_i.
  *
  * Conventions (every entry point):
@@ -129,6 +131,45 @@ typedef struct pbf_lod_desc {
     float splat;             /* DTVS: splat radius of a particle, >= 0 */
 } pbf_lod_desc;
 
+/* Solid obstacles (signed-distance shapes, Section 6) and pre-stabilisation
+ * (Section 4.3, Fig. 6; the contact lines of Fig. 7).  Each step:
+ *   - contact finding, from the predicted positions x* of every particle:
+ *     obstacle o is a contact of particle i when the obstacle grown by h
+ *     holds x*_i (sphere: the ball of radius r + h; cone: its slant moved
+ *     out by h; box: the box grown by h per axis), decided in float32;
+ *   - pre-stabilisation, stab_iters times: a particle with N_i < stab_s lying
+ *     inside a contact obstacle has x*_i moved to the closest point of the
+ *     obstacle's surface (then clamped to the walls), and x_i moved by the
+ *     same amount, so that the push-out adds no velocity;
+ *   - contact response in every update of an active particle:
+ *     x*_i + Delta p_i is moved out of each contact obstacle it lies in, in
+ *     obstacle order, before the wall clamp.
+ * Closest surface points: sphere, radially from the centre (straight up from
+ * the centre itself); box, through the face of least penetration (first axis
+ * on ties); cone (apex H above the centre, radius R at the centre's height,
+ * the slant continued below that circle: a cone standing on the floor, which
+ * fluid never leaves through its base), in the plane of the axis and the
+ * point, to the foot of the perpendicular on the slant line (on the axis the
+ * plane through +x). */
+#define PBF_MAX_OBSTACLES 4
+#define PBF_OBSTACLE_SPHERE 1 /* centre; a[0] radius */
+#define PBF_OBSTACLE_CONE 2   /* centre of the base circle; a[0] base radius, a[1] height (+y) */
+#define PBF_OBSTACLE_BOX 3    /* centre; a[0..2] half extents (axis-aligned) */
+
+typedef struct pbf_obstacle {
+    int32_t kind;      /* PBF_OBSTACLE_* */
+    float centre[3];
+    float a[3];        /* sizes as listed for the kind, > 0 where used */
+} pbf_obstacle;
+
+typedef struct pbf_contact_desc {
+    int32_t count;                              /* 0..PBF_MAX_OBSTACLES */
+    pbf_obstacle obstacles[PBF_MAX_OBSTACLES];  /* first `count` used */
+    int32_t stab_iters;                         /* pre-stabilisation iterations, 0..PBF_MAX_ITERS */
+    int32_t stab_set;                           /* S: particles with N_i < S are pre-stabilised,
+                                                   1 (none) .. the scene's n_max */
+} pbf_contact_desc;
+
 /* Statistics of the most recent step (read with pbf_stats; synchronises). */
 typedef struct pbf_step_stats {
     int32_t n_iters;                     /* loop bound: largest n_max over scenes */
@@ -180,6 +221,13 @@ pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const fl
                             const float *v0, int32_t inputs_on_device, void *hip_stream,
                             pbf_ctx **out);
 pbf_status pbf_batch_set_lod(pbf_ctx *ctx, int32_t scene, const pbf_lod_desc *lod);
+/* Obstacles and pre-stabilisation of one scene (0-based), copied; applies
+ * from the next step.  count = 0 and stab_iters = 0 remove them.  Invalid
+ * descriptors (kind, non-finite or non-positive sizes, counts out of range)
+ * give PBF_ERR_INVALID_ARG and change nothing.  A context with obstacles in
+ * any scene adds one per-particle pass after the neighbour search and keeps
+ * a byte per particle (the contact set of the last step). */
+pbf_status pbf_batch_set_obstacles(pbf_ctx *ctx, int32_t scene, const pbf_contact_desc *desc);
 /* Positions of one scene, float[3 * n_scene] in its ID order. */
 pbf_status pbf_batch_read_positions(pbf_ctx *ctx, int32_t scene, float *out,
                                     int32_t out_on_device);
@@ -223,6 +271,9 @@ pbf_status pbf_debug_neighbours(pbf_ctx *ctx, int32_t *counts, int32_t *ids, int
 pbf_status pbf_debug_lambda(pbf_ctx *ctx, float *lambda);
 /* Levels N_i used in the last step. */
 pbf_status pbf_debug_levels(pbf_ctx *ctx, uint8_t *levels);
+/* Contacts found in the last step (bit o set: obstacle o of the particle's
+ * scene); zeros where no scene has obstacles. */
+pbf_status pbf_debug_contacts(pbf_ctx *ctx, uint8_t *mask);
 /* Save / restore the dynamic state (positions and velocities, ID order,
  * host buffers float[3 * n_total] each, plus the step counter).  A restored
  * context continues bit-identically to one that never stopped. */
@@ -260,8 +311,9 @@ pbf_status pbf_rollout_forward(pbf_ctx *ctx, int32_t n_steps, int32_t ckpt_every
  * levels, neighbour sets and wall contacts held fixed (the adjoint of
  * Eqs. 4-7 and of Fig. 7's prediction and update); every segment between
  * checkpoints is recomputed from its checkpoint.  All four buffers are host
- * memory (on_device = 0, synchronises) or device memory (1).  The context
- * is left at the final state of the rollout, stored in ID order (after an
+ * memory (on_device = 0, synchronises) or device memory (1).  Scenes with
+ * obstacles are not differentiated (pbf_rollout_forward gives
+ * PBF_ERR_INVALID_ARG).  The context is left at the final state of the rollout, stored in ID order (after an
  * error its state is unspecified).  The checkpoints and the reverse pass's
  * work buffers (per recorded step: n (K+1) 16 B of positions plus the
  * neighbour codes) stay allocated in the context for the next call of the

@@ -14,10 +14,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (PBF_LOD_DTC, PBF_LOD_DTVS, PBF_LOD_EXPLICIT, PBF_LOD_UNIFORM,  # noqa: F401
-                   PBF_MAX_ITERS, PbfLodDesc, PbfParams, PbfStepStats)
+                   PBF_MAX_ITERS, PBF_MAX_OBSTACLES, PBF_OBSTACLE_BOX, PBF_OBSTACLE_CONE,
+                   PBF_OBSTACLE_SPHERE, PbfContactDesc, PbfLodDesc, PbfParams, PbfStepStats)
 
 __all__ = ["Sim", "PbfError", "make_params", "PBF_LOD_UNIFORM", "PBF_LOD_EXPLICIT",
-           "PBF_LOD_DTC", "PBF_LOD_DTVS", "kernel_names", "rollout"]
+           "PBF_LOD_DTC", "PBF_LOD_DTVS", "PBF_OBSTACLE_SPHERE", "PBF_OBSTACLE_CONE",
+           "PBF_OBSTACLE_BOX", "kernel_names", "rollout"]
 
 
 class PbfError(RuntimeError):
@@ -114,6 +116,9 @@ class Sim:
                                  up=getattr(s, "up", (0.0, 1.0, 0.0)),
                                  focal=getattr(s, "focal", 1.0), image=getattr(s, "image", (1, 1)),
                                  splat=getattr(s, "splat", 0.0))
+                if getattr(s, "obstacles", ()) or getattr(s, "stab_iters", 0):
+                    self.set_obstacles(s.obstacles, stab_iters=getattr(s, "stab_iters", 0),
+                                       stab_set=getattr(s, "stab_s", 1), scene=i)
 
     # ------------------------------------------------------------ helpers
     def _check(self, st, what):
@@ -164,6 +169,22 @@ class Sim:
         self._check(self._lib.pbf_batch_set_lod(self._ctx, int(scene), ctypes.byref(d)),
                     "pbf_batch_set_lod")
         del keep
+
+    def set_obstacles(self, obstacles=(), stab_iters: int = 0, stab_set: int = 1, scene: int = 0):
+        """Solid obstacles ((kind, centre, a) tuples, PBF_OBSTACLE_*) and
+        pre-stabilisation of the particles with N_i < stab_set."""
+        d = PbfContactDesc()
+        d.count = len(obstacles)
+        if d.count > PBF_MAX_OBSTACLES:
+            raise PbfError(-1, f"at most {PBF_MAX_OBSTACLES} obstacles")
+        for k, (kind, centre, a) in enumerate(obstacles):
+            d.obstacles[k].kind = int(kind)
+            for j in range(3):
+                d.obstacles[k].centre[j] = float(centre[j])
+                d.obstacles[k].a[j] = float(a[j])
+        d.stab_iters, d.stab_set = int(stab_iters), int(stab_set)
+        self._check(self._lib.pbf_batch_set_obstacles(self._ctx, int(scene), ctypes.byref(d)),
+                    "pbf_batch_set_obstacles")
 
     def step(self, n_steps: int = 1):
         self._check(self._lib.pbf_step(self._ctx, int(n_steps)), "pbf_step")
@@ -259,6 +280,11 @@ class Sim:
     def debug_lambda(self) -> np.ndarray:
         out = np.empty(self.n, np.float32)
         self._check(self._lib.pbf_debug_lambda(self._ctx, out.ctypes.data), "pbf_debug_lambda")
+        return out
+
+    def debug_contacts(self) -> np.ndarray:
+        out = np.zeros(self.n, np.uint8)
+        self._check(self._lib.pbf_debug_contacts(self._ctx, out.ctypes.data), "pbf_debug_contacts")
         return out
 
     def debug_levels(self) -> np.ndarray:

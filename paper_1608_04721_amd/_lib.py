@@ -29,6 +29,11 @@ PBF_LOD_DTVS = 3
 PBF_MAX_SPLAT = 16
 PBF_MAX_IMAGE = 8192
 
+PBF_MAX_OBSTACLES = 4
+PBF_OBSTACLE_SPHERE = 1
+PBF_OBSTACLE_CONE = 2
+PBF_OBSTACLE_BOX = 3
+
 c_i32, c_i64, c_u32, c_f32, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                     ctypes.c_float, ctypes.c_void_p)
 
@@ -45,6 +50,15 @@ class PbfLodDesc(ctypes.Structure):
                 ("camera", c_f32 * 3), ("d_near", c_f32), ("d_far", c_f32),
                 ("forward", c_f32 * 3), ("up", c_f32 * 3), ("focal", c_f32),
                 ("width", c_i32), ("height", c_i32), ("splat", c_f32)]
+
+
+class PbfObstacle(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("centre", c_f32 * 3), ("a", c_f32 * 3)]
+
+
+class PbfContactDesc(ctypes.Structure):
+    _fields_ = [("count", c_i32), ("obstacles", PbfObstacle * PBF_MAX_OBSTACLES),
+                ("stab_iters", c_i32), ("stab_set", c_i32)]
 
 
 class PbfStepStats(ctypes.Structure):
@@ -70,6 +84,7 @@ SIGNATURES = {
     "pbf_status_string": (ctypes.c_char_p, [c_i32]),
     "pbf_batch_create": (c_i32, [c_i32, P(PbfParams), c_vp, c_vp, c_i32, c_vp, P(CTX)]),
     "pbf_batch_set_lod": (c_i32, [CTX, c_i32, P(PbfLodDesc)]),
+    "pbf_batch_set_obstacles": (c_i32, [CTX, c_i32, P(PbfContactDesc)]),
     "pbf_batch_read_positions": (c_i32, [CTX, c_i32, c_vp, c_i32]),
     "pbf_get_counts": (c_i32, [CTX, P(c_i32), P(c_i64)]),
     "pbf_set_graph": (c_i32, [CTX, c_i32]),
@@ -84,6 +99,7 @@ SIGNATURES = {
     "pbf_debug_neighbours": (c_i32, [CTX, c_vp, c_vp, c_i64, P(c_i64)]),
     "pbf_debug_lambda": (c_i32, [CTX, c_vp]),
     "pbf_debug_levels": (c_i32, [CTX, c_vp]),
+    "pbf_debug_contacts": (c_i32, [CTX, c_vp]),
     "pbf_get_state": (c_i32, [CTX, c_vp, c_vp, P(c_i64)]),
     "pbf_set_state": (c_i32, [CTX, c_vp, c_vp, c_i64]),
     "pbf_density": (c_i32, [CTX, c_vp, c_vp, c_i32]),

@@ -588,6 +588,7 @@ pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
     s.lod_mode = lod->mode;
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->scenes[scene] = s;
+    c->roll_valid = false;  // a recorded rollout no longer replays the same steps
     // lay the depth images of all DTVS scenes out one after another
     size_t pixels = 0;
     for (auto &sd : c->scenes) {
@@ -622,6 +623,63 @@ pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
 pbf_status pbf_set_lod(pbf_ctx *c, const pbf_lod_desc *lod)
 {
     return pbf_batch_set_lod(c, 0, lod);
+}
+
+pbf_status pbf_batch_set_obstacles(pbf_ctx *c, int32_t scene, const pbf_contact_desc *desc)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (!desc || scene < 0 || scene >= c->n_scenes)
+        return fail(c, PBF_ERR_INVALID_ARG, "bad scene index or null descriptor");
+    const pbf_params &p = c->params[scene];
+    if (desc->count < 0 || desc->count > PBF_MAX_OBSTACLES)
+        return fail(c, PBF_ERR_INVALID_ARG, "obstacle count outside [0, PBF_MAX_OBSTACLES]");
+    if (desc->stab_iters < 0 || desc->stab_iters > PBF_MAX_ITERS)
+        return fail(c, PBF_ERR_INVALID_ARG, "stab_iters outside [0, PBF_MAX_ITERS]");
+    if (desc->stab_set < 1 || desc->stab_set > p.n_max)
+        return fail(c, PBF_ERR_INVALID_ARG, "stab_set outside [1, n_max]");
+    SceneDev s = c->scenes[scene];
+    for (int o = 0; o < desc->count; ++o) {
+        const pbf_obstacle &ob = desc->obstacles[o];
+        const int used = ob.kind == PBF_OBSTACLE_SPHERE ? 1 : ob.kind == PBF_OBSTACLE_CONE ? 2 : 3;
+        if (ob.kind < PBF_OBSTACLE_SPHERE || ob.kind > PBF_OBSTACLE_BOX)
+            return fail(c, PBF_ERR_INVALID_ARG, "unknown obstacle kind");
+        if (!finite3(ob.centre) || !finite3(ob.a))
+            return fail(c, PBF_ERR_INVALID_ARG, "non-finite obstacle");
+        for (int d = 0; d < used; ++d)
+            if (!(ob.a[d] > 0.f)) return fail(c, PBF_ERR_INVALID_ARG, "obstacle sizes must be > 0");
+        s.obst[o].kind = ob.kind;
+        for (int d = 0; d < 3; ++d) {
+            s.obst[o].c[d] = ob.centre[d];
+            s.obst[o].a[d] = ob.a[d];
+        }
+    }
+    for (int o = desc->count; o < kMaxObstacles; ++o) s.obst[o] = ObstacleDev{};
+    s.n_obst = desc->count;
+    s.stab_iters = desc->stab_iters;
+    s.stab_s = desc->stab_set;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    bool on = false;
+    for (int k = 0; k < c->n_scenes; ++k) {
+        const SceneDev &sd = k == scene ? s : c->scenes[k];
+        on = on || sd.n_obst > 0;
+    }
+    if (on && !c->b.contact) {
+        hipError_t e = dalloc(c, &c->b.contact, (size_t)c->n_total);
+        if (e != hipSuccess) {
+            c->b.contact = nullptr;
+            return hip_fail(c, e, "contact buffer");
+        }
+        HIPCHK(c, hipMemsetAsync(c->b.contact, 0, (size_t)std::max<int64_t>(c->n_total, 1), c->stream),
+               "clear contacts");
+    }
+    c->scenes[scene] = s;
+    c->roll_valid = false;
+    if (on != c->b.contacts_on) drop_graphs(c);  // the step's launches change
+    c->b.contacts_on = on;
+    HIPCHK(c, hipMemcpyAsync((void *)c->b.scenes, c->scenes.data(), sizeof(SceneDev) * c->scenes.size(),
+                             hipMemcpyHostToDevice, c->stream), "upload scenes");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return PBF_OK;
 }
 
 pbf_status pbf_step(pbf_ctx *c, int32_t n_steps)
@@ -960,6 +1018,23 @@ pbf_status pbf_debug_levels(pbf_ctx *c, uint8_t *levels)
     return PBF_OK;
 }
 
+pbf_status pbf_debug_contacts(pbf_ctx *c, uint8_t *mask)
+{
+    if (!c || (!mask && c->n_total)) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    if (!c->b.contacts_on) {
+        std::fill(mask, mask + c->n_total, (uint8_t)0);
+        return PBF_OK;
+    }
+    std::vector<uint8_t> m;
+    std::vector<uint32_t> id;
+    if ((st = d2h(c, m, (const uint8_t *)c->b.contact, (size_t)c->n_total)) != PBF_OK) return st;
+    if ((st = d2h(c, id, c->b.id[c->cur], (size_t)c->n_total)) != PBF_OK) return st;
+    for (size_t s = 0; s < id.size(); ++s) mask[id[s]] = m[s];
+    return PBF_OK;
+}
+
 pbf_status pbf_get_state(pbf_ctx *c, float *x, float *v, int64_t *step)
 {
     if (!c || ((!x || !v) && c->n_total)) return PBF_ERR_INVALID_ARG;
@@ -995,6 +1070,8 @@ pbf_status pbf_rollout_forward(pbf_ctx *c, int32_t n_steps, int32_t ckpt_every)
     if (!c) return PBF_ERR_INVALID_ARG;
     if (n_steps < 1 || ckpt_every < 1)
         return fail(c, PBF_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
+    if (c->b.contacts_on)
+        return fail(c, PBF_ERR_INVALID_ARG, "the rollout does not differentiate obstacle contacts");
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->roll_valid = false;
     const size_t n3 = (size_t)c->n_total * 3;

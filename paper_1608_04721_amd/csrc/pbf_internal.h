@@ -46,6 +46,14 @@ __host__ __device__ inline uint32_t make_meta(uint32_t count, uint32_t level, ui
 
 // Per-scene constants on the device.  Derived on the host in double and
 // rounded once to float.
+// A solid obstacle (PBF_OBSTACLE_*): centre and sizes as in pbf_obstacle.
+struct ObstacleDev {
+    int32_t kind;
+    float c[3];
+    float a[3];
+};
+constexpr int kMaxObstacles = 4;  // PBF_MAX_OBSTACLES
+
 struct SceneDev {
     float lo[3], hi[3];
     float h, h2, h6;
@@ -67,6 +75,9 @@ struct SceneDev {
     float fwd[3], up[3], focal, splat;
     int32_t img_w, img_h;
     uint32_t depth_off;
+    // solid obstacles and pre-stabilisation (particles with N_i < stab_s)
+    int32_t n_obst, stab_iters, stab_s;
+    ObstacleDev obst[kMaxObstacles];
 };
 
 // Device fault bits, latched in a device word.
@@ -94,6 +105,7 @@ enum Kernel : int {
     K_LAMBDA,
     K_UPDATE,
     K_COMMIT,
+    K_CONTACTS,
     K_COUNT
 };
 
@@ -169,6 +181,8 @@ struct StepBuffers {
     unsigned long long *totals;  // [0] sum of N_i over steps, [1] steps
     uint32_t *depth;         // depth images of the DTVS scenes (float bits)
     uint32_t n_depth;        // their pixels in total (0: no DTVS scene)
+    uint8_t *contact;        // [n] contacts found this step, slot order (bit o: obstacle o)
+    bool contacts_on;        // some scene has obstacles or pre-stabilisation
 };
 
 struct LaunchShape {

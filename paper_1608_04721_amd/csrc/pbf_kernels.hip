@@ -33,12 +33,12 @@ namespace pbf {
 const char *const kKernelNames[K_COUNT] = {
     "depth",        "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
     "sort_finish",  "tile_prepare", "level_count", "level_scan",  "level_scatter",
-    "tile_tables",  "neighbours",  "lambda",       "update",      "commit"};
+    "tile_tables",  "neighbours",  "lambda",       "update",      "commit",       "contacts"};
 
 const int kDefaultBlock[K_COUNT] = {256,          256,          kScanBlock,   1024,         kScanBlock,
                                     256,          256,          256,          kLevelBlock,
                                     1024,         kLevelBlock,  1024,         kNbrThreads,
-                                    kTileThreads, kTileThreads, 256};
+                                    kTileThreads, kTileThreads, 256,          256};
 
 namespace {
 
@@ -418,6 +418,123 @@ __global__ void k_sort_finish(int64_t n, const uint32_t *__restrict__ tmp_src,
     id_out[f] = my;
     lvl_out[f] = lvl_in[s];
     key_out[f] = k;
+}
+
+
+// ------------------------------------------------------------------ obstacles
+// Contact finding (Fig. 7, second loop): obstacle o is a contact when its
+// bounding volume grown by the margin m holds the predicted position;
+// decided in float32 with one rounding per operation.
+__device__ __forceinline__ bool contact_found(const ObstacleDev &o, float px, float py, float pz,
+                                              float m)
+{
+#pragma clang fp contract(off)
+    const float dx = px - o.c[0], dy = py - o.c[1], dz = pz - o.c[2];
+    if (o.kind == PBF_OBSTACLE_SPHERE) {
+        const float r = o.a[0] + m;
+        return dx * dx + dy * dy + dz * dz < r * r;
+    }
+    if (o.kind == PBF_OBSTACLE_CONE) {  // the slant moved out by m
+        const float rho = sqrtf(dx * dx + dz * dz);
+        const float L = sqrtf(o.a[1] * o.a[1] + o.a[0] * o.a[0]);
+        return rho * o.a[1] + dy * o.a[0] < o.a[1] * o.a[0] + m * L;
+    }
+    return fabsf(dx) < o.a[0] + m && fabsf(dy) < o.a[1] + m && fabsf(dz) < o.a[2] + m;
+}
+
+// Moves (x, y, z) to the closest point of the obstacle's surface when it
+// lies inside the solid (the contact's projection); returns whether it did.
+// Sphere: radially (straight up from the centre).  Box: through the face of
+// least penetration (first axis on ties).  Cone (standing on the floor, its
+// slant continued below the base circle): in the plane of the axis and the
+// point, to the foot of the perpendicular on the slant line (+x on the
+// axis).
+__device__ __forceinline__ bool obstacle_project(const ObstacleDev &o, float &x, float &y, float &z)
+{
+    const float d0 = x - o.c[0], d1 = y - o.c[1], d2 = z - o.c[2];
+    if (o.kind == PBF_OBSTACLE_SPHERE) {
+        const float R = o.a[0];
+        const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (!(r2 < R * R)) return false;
+        if (r2 > 0.f) {
+            const float s = R / sqrtf(r2);
+            x = o.c[0] + s * d0;
+            y = o.c[1] + s * d1;
+            z = o.c[2] + s * d2;
+        } else {
+            y = o.c[1] + R;
+        }
+        return true;
+    }
+    if (o.kind == PBF_OBSTACLE_CONE) {
+        const float R = o.a[0], H = o.a[1];
+        float rho = sqrtf(d0 * d0 + d2 * d2), yb = d1;
+        if (!(rho * H + yb * R < H * R)) return false;
+        const float L = sqrtf(H * H + R * R);
+        const float ds = (H * R - rho * H - yb * R) / L;  // distance to the slant line
+        const float ux = rho > 0.f ? d0 / rho : 1.f, uz = rho > 0.f ? d2 / rho : 0.f;
+        rho += ds * H / L;
+        yb += ds * R / L;
+        x = o.c[0] + rho * ux;
+        y = o.c[1] + yb;
+        z = o.c[2] + rho * uz;
+        return true;
+    }
+    const float q0 = fabsf(d0) - o.a[0], q1 = fabsf(d1) - o.a[1], q2 = fabsf(d2) - o.a[2];
+    if (!(q0 < 0.f && q1 < 0.f && q2 < 0.f)) return false;
+    if (q0 >= q1 && q0 >= q2) x = o.c[0] + (d0 >= 0.f ? o.a[0] : -o.a[0]);
+    else if (q1 >= q2) y = o.c[1] + (d1 >= 0.f ? o.a[1] : -o.a[1]);
+    else z = o.c[2] + (d2 >= 0.f ? o.a[2] : -o.a[2]);
+    return true;
+}
+
+// Contact response of an update: out of every found obstacle, in order.
+__device__ __forceinline__ void contact_response(const SceneDev &S, uint32_t mask, float &x, float &y,
+                                                 float &z)
+{
+    for (int o = 0; o < S.n_obst; ++o)
+        if ((mask >> o) & 1u) obstacle_project(S.obst[o], x, y, z);
+}
+
+// Contact finding for every particle from its predicted position, then
+// pre-stabilisation (Section 4.3, Fig. 6) of the particles with N_i <
+// stab_s: x* of a particle inside a found obstacle goes to the obstacle's
+// surface (clamped to the walls) and x moves by the same amount.  Runs after
+// the neighbour search, which used x* before these moves (Fig. 7 order).
+__global__ void k_contacts(int64_t n, const SceneDev *__restrict__ sc, float4 *__restrict__ x,
+                           float4 *__restrict__ xs, const uint8_t *__restrict__ lvl,
+                           uint8_t *__restrict__ contact)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float4 xi = x[s];
+    const SceneDev &S = sc[__float_as_int(xi.w)];
+    float4 p = xs[s];
+    uint32_t mask = 0;
+    for (int o = 0; o < S.n_obst; ++o)
+        if (contact_found(S.obst[o], p.x, p.y, p.z, S.h)) mask |= 1u << o;
+    contact[s] = (uint8_t)mask;
+    if (!mask || !((int)lvl[s] < S.stab_s)) return;
+    float mx = 0.f, my = 0.f, mz = 0.f;
+    bool moved = false;
+    for (int it = 0; it < S.stab_iters; ++it)
+        for (int o = 0; o < S.n_obst; ++o) {
+            float qx = p.x, qy = p.y, qz = p.z;
+            if (!((mask >> o) & 1u) || !obstacle_project(S.obst[o], qx, qy, qz)) continue;
+            qx = clampf(qx, S.lo[0], S.hi[0]);
+            qy = clampf(qy, S.lo[1], S.hi[1]);
+            qz = clampf(qz, S.lo[2], S.hi[2]);
+            mx += qx - p.x;
+            my += qy - p.y;
+            mz += qz - p.z;
+            p.x = qx;
+            p.y = qy;
+            p.z = qz;
+            moved = true;
+        }
+    if (!moved) return;
+    xs[s] = p;
+    x[s] = make_float4(xi.x + mx, xi.y + my, xi.z + mz, xi.w);
 }
 
 
@@ -1031,14 +1148,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
 
 // Delta p_i (Eq. 7) with the wall contact (clamp) for the active own
 // particles of a tile
-template <bool FITS>
+template <bool FITS, bool CONTACTS>
 __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const TileTables &tb,
                                             const float4 *__restrict__ stage,
                                             const float4 *__restrict__ xs_in,
                                             float4 *__restrict__ xs_out, int64_t n,
                                             const uint4 *__restrict__ nbr,
                                             const uint32_t *__restrict__ pmeta,
-                                            const uint32_t *__restrict__ pslot, uint32_t p0,
+                                            const uint32_t *__restrict__ pslot,
+                                            const uint8_t *__restrict__ contact, uint32_t p0,
                                             uint32_t nown, uint32_t first, uint32_t last)
 {
     const float h = S.h, cg = S.c_grad, sr = S.inv_rho0;
@@ -1068,8 +1186,12 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
             pz += f * dz;
         });
         const float s = -cg * sr;
-        xs_out[i] = make_float4(clampf(xi.x + px * s, lo0, hi0), clampf(xi.y + py * s, lo1, hi1),
-                                clampf(xi.z + pz * s, lo2, hi2), li);
+        float nx = xi.x + px * s, ny = xi.y + py * s, nz = xi.z + pz * s;
+        if (CONTACTS) {  // found obstacles first, then the walls
+            const uint32_t m = contact[i];
+            if (m) contact_response(S, m, nx, ny, nz);
+        }
+        xs_out[i] = make_float4(clampf(nx, lo0, hi0), clampf(ny, lo1, hi1), clampf(nz, lo2, hi2), li);
     }
 }
 
@@ -1077,14 +1199,15 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
 // (Jacobi).  Particles that finished with this iteration (N_i == k) copy
 // position and lambda across, so that both buffers hold their final values
 // from now on.
-template <bool SPLIT>
+template <bool SPLIT, bool CONTACTS>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_update(
     int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
     const uint32_t *__restrict__ rows, const float4 *__restrict__ xs_in,
     float4 *__restrict__ xs_out, int64_t n, const uint4 *__restrict__ nbr,
-    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot, uint32_t tx)
+    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot,
+    const uint8_t *__restrict__ contact, uint32_t tx)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
@@ -1096,10 +1219,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     if (stage_rows(rows, tile, xs_in, tb, stage))
-        tile_update<true>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown, first, last);
+        tile_update<true, CONTACTS>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact, p0,
+                                    nown, first, last);
     else
-        tile_update<false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, p0, nown, first,
-                           last);
+        tile_update<false, CONTACTS>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact, p0,
+                                     nown, first, last);
 }
 
 // ------------------------------------------------ average density
@@ -1370,27 +1494,32 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
         LAUNCH(K_LEVEL_SCATTER, b.n_level_blocks, kLevelBlock, k_level_scatter, T, b.tile_lvl,
                b.level_counts, b.n_level_blocks, K, b.tile_order);
     }
-    // the split variants only where the grid has room for them: the plain
-    // ones need not wait for the tile's count before staging
-#define TILE_LAUNCH(KID, KERNEL, ...)                                                       \
-    do {                                                                                  \
-        if (SPLIT > 1) LAUNCH(KID, TX * SPLIT, bs[KID], KERNEL<true>, __VA_ARGS__, TX);   \
-        else LAUNCH(KID, TX, bs[KID], KERNEL<false>, __VA_ARGS__, TX);                    \
-    } while (0)
-    TILE_LAUNCH(K_NEIGHBOURS, k_neighbours, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
-                b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap, b.nbr, b.pmeta,
-                b.pslot, b.tile_count, b.tile_rows, b.err);
+    // the split variants only where the grid has room for them (the plain
+    // ones need not wait for the tile's count before staging); contact
+    // responses only in contexts with obstacles
+    const bool split = SPLIT > 1, ct = b.contacts_on;
+    const auto nbr_kernel = split ? k_neighbours<true> : k_neighbours<false>;
+    const auto lam_kernel = split ? k_lambda<true> : k_lambda<false>;
+    const auto upd_kernel = split ? (ct ? k_update<true, true> : k_update<true, false>)
+                                  : (ct ? k_update<false, true> : k_update<false, false>);
+    LAUNCH(K_NEIGHBOURS, TX * SPLIT, bs[K_NEIGHBOURS], nbr_kernel, b.scenes, b.tile_scene,
+           b.tile_order, b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap,
+           b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX);
+    if (ct)
+        LAUNCH(K_CONTACTS, blocks_for(n, bs[K_CONTACTS]), bs[K_CONTACTS], k_contacts, n, b.scenes,
+               b.x[nxt], b.xs[0], b.lvl[nxt], b.contact);
     for (int k = 0; k < K; ++k) {
         float4 *xin = b.xs[k & 1], *xout = b.xs[(k + 1) & 1];
-        TILE_LAUNCH(K_LAMBDA, k_lambda, k, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
-                    b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr, b.pmeta, b.pslot);
+        LAUNCH(K_LAMBDA, TX * SPLIT, bs[K_LAMBDA], lam_kernel, k, b.scenes, b.tile_scene,
+               b.tile_order, b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr,
+               b.pmeta, b.pslot, TX);
         if (rec && (e = hipMemcpyAsync(rec->snap[k], xin, sizeof(float4) * n,
                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;
-        TILE_LAUNCH(K_UPDATE, k_update, k, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
-                    b.tile_start, b.tile_count, b.tile_rows, xin, xout, n, b.nbr, b.pmeta, b.pslot);
+        LAUNCH(K_UPDATE, TX * SPLIT, bs[K_UPDATE], upd_kernel, k, b.scenes, b.tile_scene,
+               b.tile_order, b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, xout, n,
+               b.nbr, b.pmeta, b.pslot, b.contact, TX);
     }
-#undef TILE_LAUNCH
     if (rec) {
         if ((e = hipMemcpyAsync(rec->snap[K], b.xs[K & 1], sizeof(float4) * n,
                                 hipMemcpyDeviceToDevice, s)) != hipSuccess ||

@@ -1,0 +1,200 @@
+"""GPU parity of obstacle contacts and pre-stabilisation (Section 4.3, Fig. 6,
+the contact lines of Fig. 7).
+
+Contact sets are integers decided in float32 by the same comparisons on both
+sides; they are compared bit for bit except for particles whose predicted
+position lies within 1e-5 of the largest box extent from the surface of a
+grown obstacle, where the oracle's FP64 prediction and the kernel's FP32 one
+may round to different sides (a contact found there cannot change the step:
+a particle must move more than h during the step to reach the obstacle).  Positions and
+velocities follow the tolerance of the other parity tests; each step of a run
+is compared from the GPU's own state (the oracle restarted from it).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (first import can be slow; keep it out of test timeouts)
+
+import oracle
+import scenes
+from parity import pos_tol
+
+pytestmark = pytest.mark.gpu
+
+SPHERE, CONE, BOX = scenes.OB_SPHERE, scenes.OB_CONE, scenes.OB_BOX
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    oracle.build(force=False)
+    from paper_1608_04721_amd import _lib
+    _lib.load()
+
+
+def _sim(sc, **kw):
+    from paper_1608_04721_amd import Sim
+    return Sim(sc, **kw)
+
+
+def _guard(sc):
+    return 1e-5 * float(np.max(sc.hi.astype(np.float64) - sc.lo.astype(np.float64)))
+
+
+def _near_bound(sc, xs):
+    """Particles whose predicted position lies within the guard of a grown
+    bounding surface of any obstacle."""
+    g, m = _guard(sc), float(sc.h)
+    near = np.zeros(len(xs), bool)
+    for kind, c, a in sc.obstacles:
+        d = xs - np.asarray(c, np.float64)
+        a = np.asarray(a, np.float64)
+        if kind == SPHERE:
+            near |= np.abs(np.linalg.norm(d, axis=1) - (a[0] + m)) <= g
+        elif kind == CONE:  # the slant moved out by m
+            L = np.hypot(a[0], a[1])
+            f = (np.hypot(d[:, 0], d[:, 2]) * a[1] + d[:, 1] * a[0] - a[0] * a[1]) / L
+            near |= np.abs(f - m) <= g
+        else:
+            near |= np.any(np.abs(np.abs(d) - (a + m)) <= g, axis=1)
+    return near
+
+
+def _compare_step(sc, sim, x, v, tol=None):
+    """One GPU step against one oracle step from the same float32 state."""
+    x_ref, v_ref, info = oracle.apbf_step(sc, x.astype(np.float64), v.astype(np.float64), trace=True)
+    sim.step(1)
+    xg = sim.positions().astype(np.float64)
+    vg = sim.velocities().astype(np.float64)
+    tol = pos_tol(sc) if tol is None else tol
+    assert np.abs(xg - x_ref).max() <= tol
+    assert np.abs(vg - v_ref).max() <= tol / float(sc.dt)
+    mask = sim.debug_contacts()
+    near = _near_bound(sc, info["xs_iter"][0])
+    bad = (mask != info["contacts"]) & ~near
+    assert not bad.any(), f"{int(bad.sum())} contact sets differ"
+    assert np.array_equal(sim.debug_levels().astype(np.int32), info["levels"])
+    return info
+
+
+def _aimed_multi_dam(speed=1.5, **kw):
+    sc = scenes.multi_dam_break(**kw)
+    (_, c, _), = sc.obstacles
+    d = np.asarray(c, np.float64) - sc.x0.astype(np.float64)
+    d[:, 1] = 0.0
+    v = speed * d / np.linalg.norm(d, axis=1, keepdims=True)
+    return dataclasses.replace(sc, v0=v.astype(np.float32))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_multi_dam_break_steps_match_oracle(graph):
+    sc = _aimed_multi_dam(a=9, ny=10, box=(1.6, 1.0, 1.6), cone=(0.35, 0.5), n_min=2, n_max=6,
+                          stab_iters=2, stab_s=5)
+    touched, stabbed = 0, 0
+    with _sim(sc) as sim:
+        sim.set_graph(graph)
+        x, v = sc.x0, sc.v0
+        for step in range(14):
+            info = _compare_step(sc, sim, x, v)
+            m = info["contacts"].astype(bool)
+            touched = max(touched, int(m.sum()))
+            stabbed = max(stabbed, int((m & (info["levels"] < sc.stab_s)).sum()))
+            x, v = sim.positions(), sim.velocities()
+    print(f"contacts up to {touched}, pre-stabilised candidates up to {stabbed}")
+    assert touched > 50 and stabbed > 20
+
+
+@pytest.mark.parametrize("kind,c,a", [(SPHERE, (0.0, 0.0, 0.0), (0.5, 0.0, 0.0)),
+                                      (BOX, (0.0, 0.0, 0.0), (0.4, 0.5, 0.3)),
+                                      (CONE, (0.0, 0.0, 0.0), (0.6, 0.55, 0.0))])
+def test_prestabilised_particle_keeps_its_velocity(kind, c, a):
+    x = np.array([[0.05, 0.53, 0.02], [1.5, 0.0, 0.0]], np.float32)
+    v = np.array([[0.0, -3.0, 0.0], [0.0, 0.0, 0.0]], np.float32)
+    sc = scenes.Scene(name="lone", x0=x, v0=v, lo=(-2, -2, -2), hi=(2, 2, 2), n_min=1, n_max=2,
+                      lod_mode=scenes.LOD_EXPLICIT, levels=np.array([1, 2], np.uint8),
+                      obstacles=((kind, c, a),), stab_iters=1, stab_s=2)
+    with _sim(sc) as sim:
+        _compare_step(sc, sim, sc.x0, sc.v0)
+        vg = sim.velocities()
+        assert sim.debug_contacts()[0] == 1
+    vpred = v[0].astype(np.float64) + float(sc.dt) * sc.gravity.astype(np.float64)
+    np.testing.assert_allclose(vg[0], vpred, rtol=0, atol=2e-4)
+
+
+def test_full_size_multi_dam_break():
+    # the 225,400-particle scene: 60 graph steps bring the blocks onto the
+    # cone; one more step against the oracle from that state
+    sc = scenes.multi_dam_break()
+    with _sim(sc) as sim:
+        sim.set_graph(True)
+        sim.step(60)
+        x, v = sim.positions(), sim.velocities()
+        info = _compare_step(sc, sim, x, v)
+    m = info["contacts"].astype(bool)
+    print(f"contacts {int(m.sum())}, pre-stabilised candidates "
+          f"{int((m & (info['levels'] < sc.stab_s)).sum())}")
+    assert m.sum() > 1000
+
+
+def test_batch_with_and_without_obstacles():
+    a = _aimed_multi_dam(a=6, ny=7, box=(1.2, 0.8, 1.2), cone=(0.3, 0.4), n_min=2, n_max=5,
+                         stab_iters=1, stab_s=4)
+    b = scenes.dam_break_4k()
+    c = dataclasses.replace(scenes.block(8, 6, 8, seed=9, n_min=1, n_max=4, levels="random"),
+                            obstacles=((SPHERE, (0.2, 0.1, 0.2), (0.15, 0, 0)),
+                                       (BOX, (0.35, 0.05, 0.1), (0.05, 0.05, 0.05))),
+                            stab_iters=3, stab_s=3)
+    scs = [a, b, c]
+    with _sim(scs) as sim:
+        sim.step(6)
+        xb, mb = sim.positions(), sim.debug_contacts()
+        off = sim.offsets
+    assert mb[off[1]:off[2]].sum() == 0 and mb[off[2]:].any()
+    for i, sc in enumerate(scs):
+        with _sim(sc) as one:
+            one.step(6)
+            assert np.array_equal(one.positions(), xb[off[i]:off[i + 1]])
+            assert np.array_equal(one.debug_contacts(), mb[off[i]:off[i + 1]])
+
+
+def test_removing_obstacles_restores_the_plain_step():
+    sc = _aimed_multi_dam(a=6, ny=7, box=(1.2, 0.8, 1.2), cone=(0.3, 0.4), n_min=2, n_max=5,
+                          stab_iters=1, stab_s=4)
+    plain = dataclasses.replace(sc, obstacles=(), stab_iters=0, stab_s=1)
+    with _sim(sc) as a, _sim(plain) as b:
+        a.set_graph(True)
+        b.set_graph(True)
+        a.step(2)
+        b.set_state(*a.get_state())
+        a.set_obstacles(())
+        a.step(3)
+        b.step(3)
+        assert np.array_equal(a.positions(), b.positions())
+        assert not a.debug_contacts().any()
+
+
+def test_invalid_descriptors_and_rollout():
+    from paper_1608_04721_amd import PbfError
+    sc = scenes.dam_break_4k()
+    good = [(SPHERE, (0.5, 0.5, 0.5), (0.2, 0.0, 0.0))]
+    with _sim(sc) as sim:
+        sim.set_obstacles(good, stab_iters=1, stab_set=2)
+        for obs, kw in [([(9, (0, 0, 0), (1, 1, 1))], {}),
+                        ([(SPHERE, (np.nan, 0, 0), (1, 0, 0))], {}),
+                        ([(SPHERE, (0, 0, 0), (0.0, 0, 0))], {}),
+                        ([(CONE, (0, 0, 0), (1.0, -1.0, 0))], {}),
+                        ([(BOX, (0, 0, 0), (1.0, 1.0, 0.0))], {}),
+                        (good * 5, {}),
+                        (good, dict(stab_set=0)),
+                        (good, dict(stab_set=sc.n_max + 1)),
+                        (good, dict(stab_iters=-1))]:
+            with pytest.raises(PbfError) as e:
+                sim.set_obstacles(obs, **{"stab_iters": 1, "stab_set": 2, **kw})
+            assert e.value.status == -1
+        sim.step(1)  # still usable with the last valid descriptor
+        with pytest.raises(PbfError) as e:
+            sim.rollout_forward(2, 1)
+        assert e.value.status == -1
