@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("dims", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("mass", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double),
-                ("g", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("unilateral", ctypes.c_int32)]
 
 
 class Lod(ctypes.Structure):
@@ -49,7 +49,9 @@ class Lod(ctypes.Structure):
                 ("d_far", ctypes.c_double), ("forward", ctypes.c_double * 3),
                 ("up", ctypes.c_double * 3), ("focal", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("splat", ctypes.c_double)]
+                ("splat", ctypes.c_double), ("n_extra", ctypes.c_int32),
+                ("extra_camera", (ctypes.c_double * 3) * 3),
+                ("extra_range", (ctypes.c_double * 2) * 3), ("auto_range", ctypes.c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -154,6 +156,7 @@ def params(scene, n=None, n_min=None, n_max=None) -> Params:
         p.g[d] = float(scene.gravity[d])
     p.h, p.rho0, p.mass = float(scene.h), float(scene.rho0), float(scene.mass)
     p.eps, p.dt = float(scene.eps), float(scene.dt)
+    p.unilateral = int(bool(getattr(scene, "unilateral", False)))
     return p
 
 
@@ -175,6 +178,13 @@ class _LodHolder:
         w, h = getattr(scene, "image", (1, 1))
         self.lod.width, self.lod.height = int(w), int(h)
         self.lod.splat = float(getattr(scene, "splat", 0.0))
+        extra = getattr(scene, "extra_cameras", ())
+        self.lod.n_extra = len(extra)
+        for k, (cam, (dn, df)) in enumerate(extra):
+            for d in range(3):
+                self.lod.extra_camera[k][d] = float(cam[d])
+            self.lod.extra_range[k][0], self.lod.extra_range[k][1] = float(dn), float(df)
+        self.lod.auto_range = int(bool(getattr(scene, "auto_range", False)))
 
 
 def _obstacle(kind, centre, a) -> Obstacle:

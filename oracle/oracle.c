@@ -49,6 +49,12 @@
  *     N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max), decided
  *     in float32 like the kernel (an integer chosen by floating point is
  *     chosen in the same precision on both sides); everything else is FP64.
+ *     A t that is not a number (a range of zero width) counts as 0.  Several
+ *     cameras blend by taking the highest level; an automatic range is the
+ *     min/max of the distances over the particles at the step's start
+ *     (Section 4.1).
+ *   - Unilateral density constraint (an option; the variant named at the
+ *     end of Section 7's setup): C_i = max(rho_i/rho0 - 1, 0).
  * Neighbour sums run in ascending particle-ID order, so results do not
  * depend on any storage order.
  */
@@ -71,6 +77,7 @@ typedef struct {
     double lo[3], hi[3];
     double h, rho0, mass, eps, dt;
     double g[3];
+    int32_t unilateral;     /* 1: C_i = max(rho_i / rho0 - 1, 0) (resists compression only) */
 } orc_params;
 
 typedef struct {
@@ -86,6 +93,14 @@ typedef struct {
     double focal;
     int32_t width, height;
     double splat;
+    /* distance to camera with several cameras: the level is the highest of
+     * the levels the cameras give (the particle gets the detail the nearest
+     * view asks for); camera 0 is `camera` with d_near/d_far */
+    int32_t n_extra;        /* further cameras, 0..3 */
+    double extra_camera[3][3];
+    double extra_range[3][2];  /* d_near, d_far of each */
+    int32_t auto_range;     /* 1: each camera's range is the min/max of its distances over
+                               the particles (DTVS: over the particles seen), every step */
 } orc_lod;
 
 typedef struct {
@@ -290,6 +305,7 @@ static double lambda_of(const orc_params *p, const double *xs, int32_t i,
         gi[2] += p->mass / p->rho0 * gw[2];
     }
     double C = rho / p->rho0 - 1.0;
+    if (p->unilateral && C < 0.0) C = 0.0;
     double denom = w * (gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2]) + sum_wj;
     if (rho_out) *rho_out = rho;
     if (s_out) *s_out = denom;
@@ -445,10 +461,10 @@ static void contact_response(const orc_params *p, const orc_contacts *oc, uint32
 /* Level from a distance (DTC and DTVS, Section 4.1): linear map of the
  * distance range [d_near, d_far] onto the levels n_max .. n_min, decided in
  * float32 like the kernel. */
-static int32_t level_of_distance(const orc_params *p, const orc_lod *lod, float d)
+static int32_t level_of_distance(const orc_params *p, float d, float d_near, float d_far)
 {
-    float t = (d - (float)lod->d_near) / ((float)lod->d_far - (float)lod->d_near);
-    if (t < 0.0f) t = 0.0f;
+    float t = (d - d_near) / (d_far - d_near);
+    if (!(t >= 0.0f)) t = 0.0f;  /* negative, or not a number */
     if (t > 1.0f) t = 1.0f;
     int32_t L = p->n_max - (int32_t)floorf(t * (float)(p->n_max - p->n_min + 1));
     if (L < p->n_min) L = p->n_min;
@@ -527,14 +543,74 @@ static int levels_dtvs(const orc_params *p, const orc_lod *lod, const double *x,
                 if (a >= 0 && a < W && b >= 0 && b < H && o.dist < depth[(int64_t)b * W + a])
                     depth[(int64_t)b * W + a] = o.dist;
     }
+    float *dist = (float *)malloc(sizeof(float) * (size_t)(p->n ? p->n : 1));
+    if (!dist) { free(depth); return ORC_ERR_MEM; }
+    float dn = (float)lod->d_near, df = (float)lod->d_far;
+    if (lod->auto_range) { dn = FLT_MAX; df = 0.0f; }
     for (int32_t i = 0; i < p->n; ++i) {
         orc_proj o;
         float d = FLT_MAX;
-        if (dtvs_project(lod, x + 3 * (int64_t)i, &o) && o.pu >= 0 && o.pu < W && o.pv >= 0 && o.pv < H)
+        if (dtvs_project(lod, x + 3 * (int64_t)i, &o) && o.pu >= 0 && o.pu < W && o.pv >= 0 && o.pv < H) {
             d = o.dist - depth[(int64_t)o.pv * W + o.pu];
-        lev[i] = level_of_distance(p, lod, d);
+            if (lod->auto_range) {  /* over the particles seen */
+                if (d < dn) dn = d;
+                if (d > df) df = d;
+            }
+        }
+        dist[i] = d;
     }
+    if (df < dn) dn = df = 0.0f;  /* automatic range with no particle seen */
+    for (int32_t i = 0; i < p->n; ++i) lev[i] = level_of_distance(p, dist[i], dn, df);
+    free(dist);
     free(depth);
+    return ORC_OK;
+}
+
+/* Distance of a particle to a camera, float32 with a fixed order. */
+static float camera_distance(const double *xi, const double *cam)
+{
+    float dx = (float)xi[0] - (float)cam[0];
+    float dy = (float)xi[1] - (float)cam[1];
+    float dz = (float)xi[2] - (float)cam[2];
+    float d2 = dx * dx;
+    d2 = d2 + dy * dy;
+    d2 = d2 + dz * dz;
+    return sqrtf(d2);
+}
+
+/* Distance-to-camera levels over 1 + n_extra cameras: each camera maps its
+ * distance through its range (given, or the min/max over the particles);
+ * the particle takes the highest of the levels. */
+static int levels_dtc(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+{
+    const int nc = 1 + lod->n_extra;
+    if (lod->n_extra < 0 || lod->n_extra > 3) return ORC_ERR_ARG;
+    const double *cam[4] = {lod->camera, lod->extra_camera[0], lod->extra_camera[1], lod->extra_camera[2]};
+    float dn[4], df[4];
+    dn[0] = (float)lod->d_near;
+    df[0] = (float)lod->d_far;
+    for (int c = 1; c < nc; ++c) {
+        dn[c] = (float)lod->extra_range[c - 1][0];
+        df[c] = (float)lod->extra_range[c - 1][1];
+    }
+    if (lod->auto_range)
+        for (int c = 0; c < nc; ++c) {
+            dn[c] = FLT_MAX;
+            df[c] = 0.0f;
+            for (int32_t i = 0; i < p->n; ++i) {
+                const float d = camera_distance(x + 3 * (int64_t)i, cam[c]);
+                if (d < dn[c]) dn[c] = d;
+                if (d > df[c]) df[c] = d;
+            }
+        }
+    for (int32_t i = 0; i < p->n; ++i) {
+        int32_t L = 0;
+        for (int c = 0; c < nc; ++c) {
+            const int32_t Lc = level_of_distance(p, camera_distance(x + 3 * (int64_t)i, cam[c]), dn[c], df[c]);
+            if (Lc > L) L = Lc;
+        }
+        lev[i] = L;
+    }
     return ORC_OK;
 }
 
@@ -547,27 +623,19 @@ int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t
             if (lev[i] < 1 || lev[i] < p->n_min || lev[i] > p->n_max) return ORC_ERR_ARG;
         return ORC_OK;
     }
+    if (lod->mode == 2) {
+        /* The level is an integer decided by floating point, so it is
+         * decided in the kernel's precision: float32, one rounding per
+         * operation (no contraction), correctly rounded sqrt and division,
+         * in this order. */
+        int rc = levels_dtc(p, lod, x, lev);
+        if (rc) return rc;
+        for (int32_t i = 0; i < p->n; ++i)
+            if (lev[i] < 1 || lev[i] < p->n_min || lev[i] > p->n_max) return ORC_ERR_ARG;
+        return ORC_OK;
+    }
     for (int32_t i = 0; i < p->n; ++i) {
-        int32_t L;
-        if (lod->mode == 0) {
-            L = p->n_max;
-        } else if (lod->mode == 1) {
-            L = lod->levels[i];
-        } else {
-            /* The level is an integer decided by floating point, so it is
-             * decided in the kernel's precision: float32, one rounding per
-             * operation (no contraction), correctly rounded sqrt and division,
-             * in this order. */
-            const double *xi = x + 3 * (int64_t)i;
-            float dx = (float)xi[0] - (float)lod->camera[0];
-            float dy = (float)xi[1] - (float)lod->camera[1];
-            float dz = (float)xi[2] - (float)lod->camera[2];
-            float d2 = dx * dx;
-            d2 = d2 + dy * dy;
-            d2 = d2 + dz * dz;
-            float d = sqrtf(d2);
-            L = level_of_distance(p, lod, d);
-        }
+        int32_t L = lod->mode == 0 ? p->n_max : lod->levels[i];
         if (L < 1 || L < p->n_min || L > p->n_max) return ORC_ERR_ARG;
         lev[i] = L;
     }

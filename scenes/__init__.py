@@ -103,6 +103,12 @@ class Scene:
     obstacles: tuple = ()
     stab_iters: int = 0
     stab_s: int = 1
+    # distance-to-camera levels from further cameras ((camera, (d_near,
+    # d_far)) pairs; the particle takes the highest level), ranges found
+    # automatically every step, and the unilateral density constraint
+    extra_cameras: tuple = ()
+    auto_range: bool = False
+    unilateral: bool = False
 
     def __post_init__(self):
         self.x0 = np.ascontiguousarray(self.x0, dtype=F32).reshape(-1, 3)
@@ -125,6 +131,8 @@ class Scene:
             self.levels = np.ascontiguousarray(self.levels, dtype=np.uint8)
         self.obstacles = tuple((int(k), tuple(F32(v) for v in c), tuple(F32(v) for v in a))
                                for k, c, a in self.obstacles)
+        self.extra_cameras = tuple((tuple(F32(v) for v in cam), (F32(r[0]), F32(r[1])))
+                                   for cam, r in self.extra_cameras)
 
     @property
     def n(self) -> int:
