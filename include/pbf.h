@@ -84,6 +84,12 @@ typedef enum {
                               ray, recomputed each step likewise */
 #define PBF_MAX_SPLAT 16   /* largest splat radius in pixels (DTVS) */
 #define PBF_MAX_IMAGE 8192 /* largest DTVS image side in pixels */
+#define PBF_MAX_CAMERAS 4  /* DTC: `camera` and up to 3 further cameras */
+
+/* pbf_params.flags */
+#define PBF_FLAG_UNILATERAL 1u /* unilateral density constraint C_i = max(rho_i/rho0 - 1, 0):
+                                  resists compression only (the variant named in the
+                                  paper's evaluation setup, Section 7) */
 
 /* Per-scene parameters.  All lengths in the same unit as positions. */
 typedef struct pbf_params {
@@ -99,7 +105,7 @@ typedef struct pbf_params {
     float gravity[3];       /* external acceleration */
     int32_t max_neighbours; /* neighbour capacity; 0 => PBF_DEFAULT_NEIGHBOURS; the
                                context uses the largest value over its scenes */
-    uint32_t flags;         /* reserved, must be 0 */
+    uint32_t flags;         /* PBF_FLAG_* bits; others must be 0 */
 } pbf_params;
 
 /* Level source (Section 4.1).  A distance d is mapped to a level by
@@ -118,7 +124,16 @@ typedef struct pbf_params {
  * (2 r + 1)^2 pixels, r = min(ceil(focal splat / z), PBF_MAX_SPLAT), keeping
  * per pixel the smallest |q|.  d = |q| minus that depth at the particle's
  * own pixel (the particles seen there are the surface); particles behind
- * the camera or outside the image get the lowest level. */
+ * the camera or outside the image get the lowest level.
+ *
+ * Several cameras (DTC, Section 4.1): each of `camera` and the
+ * n_extra_cameras further ones maps its own distance through its own range;
+ * the particle takes the highest of these levels.  Automatic range
+ * (auto_range = 1, DTC and DTVS): every step, each camera's d_near and d_far
+ * are the smallest and largest of its distances over the scene's particles
+ * at the start of the step (DTVS: over the particles seen; [0, 0] when none
+ * is); the given ranges are then ignored.  A t that is not a number (a range
+ * of zero width) counts as 0. */
 typedef struct pbf_lod_desc {
     int32_t mode;            /* PBF_LOD_* */
     const uint8_t *levels;   /* EXPLICIT: n levels in [n_min, n_max], particle-ID order */
@@ -129,6 +144,10 @@ typedef struct pbf_lod_desc {
     float focal;             /* DTVS: > 0 */
     int32_t width, height;   /* DTVS: image in pixels, 1 .. PBF_MAX_IMAGE */
     float splat;             /* DTVS: splat radius of a particle, >= 0 */
+    int32_t n_extra_cameras; /* DTC: 0 .. PBF_MAX_CAMERAS - 1 */
+    float extra_camera[PBF_MAX_CAMERAS - 1][3];
+    float extra_range[PBF_MAX_CAMERAS - 1][2]; /* d_near, d_far of each (d_far > d_near) */
+    int32_t auto_range;      /* DTC, DTVS: 0 or 1 */
 } pbf_lod_desc;
 
 /* Solid obstacles (signed-distance shapes, Section 6) and pre-stabilisation
@@ -312,8 +331,8 @@ pbf_status pbf_rollout_forward(pbf_ctx *ctx, int32_t n_steps, int32_t ckpt_every
  * Eqs. 4-7 and of Fig. 7's prediction and update); every segment between
  * checkpoints is recomputed from its checkpoint.  All four buffers are host
  * memory (on_device = 0, synchronises) or device memory (1).  Scenes with
- * obstacles are not differentiated (pbf_rollout_forward gives
- * PBF_ERR_INVALID_ARG).  The context is left at the final state of the rollout, stored in ID order (after an
+ * obstacles or the unilateral constraint are not differentiated
+ * (pbf_rollout_forward gives PBF_ERR_INVALID_ARG).  The context is left at the final state of the rollout, stored in ID order (after an
  * error its state is unspecified).  The checkpoints and the reverse pass's
  * work buffers (per recorded step: n (K+1) 16 B of positions plus the
  * neighbour codes) stay allocated in the context for the next call of the

@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (PBF_LOD_DTC, PBF_LOD_DTVS, PBF_LOD_EXPLICIT, PBF_LOD_UNIFORM,  # noqa: F401
+from ._lib import (PBF_FLAG_UNILATERAL, PBF_LOD_DTC, PBF_LOD_DTVS,  # noqa: F401
+                   PBF_LOD_EXPLICIT, PBF_LOD_UNIFORM, PBF_MAX_CAMERAS,
                    PBF_MAX_ITERS, PBF_MAX_OBSTACLES, PBF_OBSTACLE_BOX, PBF_OBSTACLE_CONE,
                    PBF_OBSTACLE_SPHERE, PbfContactDesc, PbfLodDesc, PbfParams, PbfStepStats)
 
@@ -34,7 +35,8 @@ def _f32(a):
 
 def make_params(src, max_neighbours: int = 0) -> PbfParams:
     """pbf_params from any object with the scene attributes (n, n_min, n_max,
-    dims, lo, hi, h, rho0, mass, eps, dt, gravity)."""
+    dims, lo, hi, h, rho0, mass, eps, dt, gravity, and optionally
+    unilateral)."""
     p = PbfParams()
     p.n = int(src.n)
     p.n_min, p.n_max = int(src.n_min), int(src.n_max)
@@ -47,7 +49,7 @@ def make_params(src, max_neighbours: int = 0) -> PbfParams:
     p.h, p.rho0, p.mass = float(src.h), float(src.rho0), float(src.mass)
     p.eps, p.dt = float(src.eps), float(src.dt)
     p.max_neighbours = int(max_neighbours)
-    p.flags = 0
+    p.flags = PBF_FLAG_UNILATERAL if getattr(src, "unilateral", False) else 0
     return p
 
 
@@ -115,7 +117,9 @@ class Sim:
                                  scene=i, forward=getattr(s, "forward", (0.0, 0.0, 1.0)),
                                  up=getattr(s, "up", (0.0, 1.0, 0.0)),
                                  focal=getattr(s, "focal", 1.0), image=getattr(s, "image", (1, 1)),
-                                 splat=getattr(s, "splat", 0.0))
+                                 splat=getattr(s, "splat", 0.0),
+                                 extra_cameras=getattr(s, "extra_cameras", ()),
+                                 auto_range=getattr(s, "auto_range", False))
                 if getattr(s, "obstacles", ()) or getattr(s, "stab_iters", 0):
                     self.set_obstacles(s.obstacles, stab_iters=getattr(s, "stab_iters", 0),
                                        stab_set=getattr(s, "stab_s", 1), scene=i)
@@ -145,9 +149,21 @@ class Sim:
 
     # ------------------------------------------------------------ core
     def set_lod(self, mode, levels=None, camera=None, d_near=0.0, d_far=1.0, scene=0,
-                forward=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), focal=1.0, image=(1, 1), splat=0.0):
+                forward=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), focal=1.0, image=(1, 1), splat=0.0,
+                extra_cameras=(), auto_range=False):
+        """Level source of one scene (PBF_LOD_*).  extra_cameras: further DTC
+        cameras as (camera, (d_near, d_far)) pairs; auto_range: ranges found
+        every step from the particles."""
         d = PbfLodDesc()
         d.mode = int(mode)
+        if len(extra_cameras) > PBF_MAX_CAMERAS - 1:
+            raise PbfError(-1, f"at most {PBF_MAX_CAMERAS - 1} further cameras")
+        d.n_extra_cameras = len(extra_cameras)
+        for k, (cam, (dn, df)) in enumerate(extra_cameras):
+            for a in range(3):
+                d.extra_camera[k][a] = float(cam[a])
+            d.extra_range[k][0], d.extra_range[k][1] = float(dn), float(df)
+        d.auto_range = int(bool(auto_range))
         for a in range(3):
             d.forward[a] = float(forward[a])
             d.up[a] = float(up[a])

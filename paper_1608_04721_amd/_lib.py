@@ -28,6 +28,8 @@ PBF_LOD_DTC = 2
 PBF_LOD_DTVS = 3
 PBF_MAX_SPLAT = 16
 PBF_MAX_IMAGE = 8192
+PBF_MAX_CAMERAS = 4
+PBF_FLAG_UNILATERAL = 1
 
 PBF_MAX_OBSTACLES = 4
 PBF_OBSTACLE_SPHERE = 1
@@ -49,7 +51,9 @@ class PbfLodDesc(ctypes.Structure):
     _fields_ = [("mode", c_i32), ("levels", c_vp), ("levels_on_device", c_i32),
                 ("camera", c_f32 * 3), ("d_near", c_f32), ("d_far", c_f32),
                 ("forward", c_f32 * 3), ("up", c_f32 * 3), ("focal", c_f32),
-                ("width", c_i32), ("height", c_i32), ("splat", c_f32)]
+                ("width", c_i32), ("height", c_i32), ("splat", c_f32),
+                ("n_extra_cameras", c_i32), ("extra_camera", (c_f32 * 3) * (PBF_MAX_CAMERAS - 1)),
+                ("extra_range", (c_f32 * 2) * (PBF_MAX_CAMERAS - 1)), ("auto_range", c_i32)]
 
 
 class PbfObstacle(ctypes.Structure):

@@ -97,6 +97,7 @@ struct pbf_ctx {
     int32_t roll_steps = 0, roll_every = 0;
     bool roll_valid = false;
     size_t depth_cap = 0;  // pixels allocated in b.depth (DTVS depth images)
+    uint32_t range_cap = 0;  // words allocated in b.range (automatic distance ranges)
     // average-density buffers (allocated by the first pbf_density)
     pbf::DensityBuffers dens{};
     float *dens_rho_id = nullptr;
@@ -164,7 +165,7 @@ pbf_status check_params(const pbf_params &p, int32_t idx, std::string &msg, int3
         if (!std::isfinite(f)) return bad("non-finite parameter");
     if (!(p.h > 0.f) || !(p.rho0 > 0.f) || !(p.mass > 0.f) || !(p.eps >= 0.f) || !(p.dt > 0.f))
         return bad("need h, rho0, mass, dt > 0 and eps >= 0");
-    if (p.flags != 0) return bad("flags must be 0");
+    if (p.flags & ~PBF_FLAG_UNILATERAL) return bad("unknown flags");
     if (p.max_neighbours < 0 || p.max_neighbours > 4096) return bad("max_neighbours outside [0, 4096]");
     for (int d = 0; d < 3; ++d) {
         if (!(p.box_hi[d] >= p.box_lo[d])) return bad("box_hi < box_lo");
@@ -206,6 +207,11 @@ SceneDev make_scene(const pbf_params &p, const int32_t dims[3], uint32_t cell_of
     s.lod_mode = PBF_LOD_UNIFORM;
     s.d_near = 0.f;
     s.d_far = 1.f;
+    s.n_cam = 1;
+    s.rng[0][0] = 0.f;
+    s.rng[0][1] = 1.f;
+    s.stab_s = 1;
+    s.c_floor = (p.flags & PBF_FLAG_UNILATERAL) ? 0.f : -INFINITY;
     return s;
 }
 
@@ -555,19 +561,44 @@ pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
         st = check_levels(c, scene, lv.data());
         if (st != PBF_OK) return st;
     } else if (lod->mode == PBF_LOD_DTC) {
-        if (!finite3(lod->camera) || !std::isfinite(lod->d_near) || !std::isfinite(lod->d_far) ||
-            !(lod->d_far > lod->d_near))
+        if (lod->auto_range != 0 && lod->auto_range != 1)
+            return fail(c, PBF_ERR_INVALID_ARG, "auto_range must be 0 or 1");
+        if (lod->n_extra_cameras < 0 || lod->n_extra_cameras > PBF_MAX_CAMERAS - 1)
+            return fail(c, PBF_ERR_INVALID_ARG, "n_extra_cameras outside [0, PBF_MAX_CAMERAS - 1]");
+        const auto range_ok = [&](float dn, float df) {
+            return std::isfinite(dn) && std::isfinite(df) && (lod->auto_range || df > dn);
+        };
+        if (!finite3(lod->camera) || !range_ok(lod->d_near, lod->d_far))
             return fail(c, PBF_ERR_INVALID_ARG, "DTC needs a finite camera and d_far > d_near");
+        for (int k = 0; k < lod->n_extra_cameras; ++k)
+            if (!finite3(lod->extra_camera[k]) ||
+                !range_ok(lod->extra_range[k][0], lod->extra_range[k][1]))
+                return fail(c, PBF_ERR_INVALID_ARG, "DTC needs finite cameras and d_far > d_near");
         for (int d = 0; d < 3; ++d) s.cam[d] = lod->camera[d];
         s.d_near = lod->d_near;
         s.d_far = lod->d_far;
+        s.n_cam = 1 + lod->n_extra_cameras;
+        for (int k = 0; k < s.n_cam; ++k) {
+            for (int d = 0; d < 3; ++d) s.cams[k][d] = k ? lod->extra_camera[k - 1][d] : lod->camera[d];
+            s.rng[k][0] = k ? lod->extra_range[k - 1][0] : lod->d_near;
+            s.rng[k][1] = k ? lod->extra_range[k - 1][1] : lod->d_far;
+        }
+        s.auto_range = lod->auto_range;
     } else if (lod->mode == PBF_LOD_DTVS) {
         const auto fin = [](float v) { return std::isfinite(v); };
+        if (lod->auto_range != 0 && lod->auto_range != 1)
+            return fail(c, PBF_ERR_INVALID_ARG, "auto_range must be 0 or 1");
+        if (lod->n_extra_cameras != 0)
+            return fail(c, PBF_ERR_INVALID_ARG, "further cameras are for DTC only");
         if (!finite3(lod->camera) || !finite3(lod->forward) || !finite3(lod->up) ||
             !fin(lod->focal) || !(lod->focal > 0.f) || !fin(lod->splat) || !(lod->splat >= 0.f) ||
-            !fin(lod->d_near) || !fin(lod->d_far) || !(lod->d_far > lod->d_near))
+            !fin(lod->d_near) || !fin(lod->d_far) || !(lod->auto_range || lod->d_far > lod->d_near))
             return fail(c, PBF_ERR_INVALID_ARG, "DTVS needs a finite camera frame, focal > 0, "
                                                 "splat >= 0 and d_far > d_near");
+        s.n_cam = 1;
+        s.rng[0][0] = lod->d_near;
+        s.rng[0][1] = lod->d_far;
+        s.auto_range = lod->auto_range;
         if (lod->width < 1 || lod->height < 1 || lod->width > PBF_MAX_IMAGE ||
             lod->height > PBF_MAX_IMAGE)
             return fail(c, PBF_ERR_INVALID_ARG, "DTVS image size outside [1, PBF_MAX_IMAGE]");
@@ -611,6 +642,22 @@ pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
         c->depth_cap = pixels;
     }
     c->b.n_depth = (uint32_t)pixels;
+    // and the automatic-range words of every such scene's cameras
+    uint32_t words = 0;
+    for (auto &sd : c->scenes) {
+        sd.range_off = words;
+        if (sd.auto_range && (sd.lod_mode == PBF_LOD_DTC || sd.lod_mode == PBF_LOD_DTVS))
+            words += 2u * (uint32_t)sd.n_cam;
+    }
+    if (words != c->b.n_range) drop_graphs(c);
+    if (words > c->range_cap) {
+        uint32_t *r = nullptr;
+        hipError_t e = dalloc(c, &r, (size_t)words);
+        if (e != hipSuccess) return hip_fail(c, e, "range words");
+        c->b.range = r;  // the old words stay with the context's allocations
+        c->range_cap = words;
+    }
+    c->b.n_range = words;
     if (!lv.empty())
         HIPCHK(c, hipMemcpyAsync(c->b.lev_by_id + c->pid_off[scene], lv.data(), lv.size(),
                                  hipMemcpyHostToDevice, c->stream), "upload levels");
@@ -1072,6 +1119,10 @@ pbf_status pbf_rollout_forward(pbf_ctx *c, int32_t n_steps, int32_t ckpt_every)
         return fail(c, PBF_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
     if (c->b.contacts_on)
         return fail(c, PBF_ERR_INVALID_ARG, "the rollout does not differentiate obstacle contacts");
+    for (const pbf_params &p : c->params)
+        if (p.flags & PBF_FLAG_UNILATERAL)
+            return fail(c, PBF_ERR_INVALID_ARG,
+                        "the rollout does not differentiate the unilateral constraint");
     HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
     c->roll_valid = false;
     const size_t n3 = (size_t)c->n_total * 3;

@@ -53,6 +53,7 @@ struct ObstacleDev {
     float a[3];
 };
 constexpr int kMaxObstacles = 4;  // PBF_MAX_OBSTACLES
+constexpr int kMaxCameras = 4;    // PBF_MAX_CAMERAS
 
 struct SceneDev {
     float lo[3], hi[3];
@@ -78,6 +79,14 @@ struct SceneDev {
     // solid obstacles and pre-stabilisation (particles with N_i < stab_s)
     int32_t n_obst, stab_iters, stab_s;
     ObstacleDev obst[kMaxObstacles];
+    // distance-to-camera cameras (cams[0] = cam) with their ranges; with
+    // auto_range the ranges are found every step, into the range words at
+    // range_off (min, max float bits per camera)
+    int32_t n_cam, auto_range;
+    float cams[kMaxCameras][3];
+    float rng[kMaxCameras][2];
+    uint32_t range_off;
+    float c_floor;  // lower bound of C_i: 0 (unilateral) or -infinity
 };
 
 // Device fault bits, latched in a device word.
@@ -106,6 +115,7 @@ enum Kernel : int {
     K_UPDATE,
     K_COMMIT,
     K_CONTACTS,
+    K_LOD_RANGE,
     K_COUNT
 };
 
@@ -183,6 +193,8 @@ struct StepBuffers {
     uint32_t n_depth;        // their pixels in total (0: no DTVS scene)
     uint8_t *contact;        // [n] contacts found this step, slot order (bit o: obstacle o)
     bool contacts_on;        // some scene has obstacles or pre-stabilisation
+    uint32_t *range;         // automatic distance ranges (min, max float bits per camera)
+    uint32_t n_range;        // their words (0: no scene with an automatic range)
 };
 
 struct LaunchShape {

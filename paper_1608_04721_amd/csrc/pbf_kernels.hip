@@ -33,12 +33,14 @@ namespace pbf {
 const char *const kKernelNames[K_COUNT] = {
     "depth",        "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
     "sort_finish",  "tile_prepare", "level_count", "level_scan",  "level_scatter",
-    "tile_tables",  "neighbours",  "lambda",       "update",      "commit",       "contacts"};
+    "tile_tables",  "neighbours",  "lambda",       "update",      "commit",       "contacts",
+    "lod_range"};
 
 const int kDefaultBlock[K_COUNT] = {256,          256,          kScanBlock,   1024,         kScanBlock,
                                     256,          256,          256,          kLevelBlock,
                                     1024,         kLevelBlock,  1024,         kNbrThreads,
-                                    kTileThreads, kTileThreads, 256,          256};
+                                    kTileThreads, kTileThreads, 256,          256,
+                                    256};
 
 namespace {
 
@@ -104,21 +106,48 @@ __device__ __forceinline__ int level_of_distance(float d, float d_near, float d_
 {
 #pragma clang fp contract(off)
     float t = (d - d_near) / (d_far - d_near);
-    t = fminf(fmaxf(t, 0.f), 1.f);
+    t = fminf(fmaxf(t, 0.f), 1.f);  // not a number (zero-width range) -> 0
     const int L = nmax - (int)floorf(t * (float)(nmax - nmin + 1));
     return min(max(L, nmin), nmax);
 }
 
-// Distance-to-camera level (DTC)
-__device__ __forceinline__ int dtc_level(float x, float y, float z, float cx, float cy, float cz,
-                                         float d_near, float d_far, int nmin, int nmax)
+// Distance to a camera, float32 in a fixed order
+__device__ __forceinline__ float camera_distance(float x, float y, float z, const float *c)
 {
 #pragma clang fp contract(off)
-    const float dx = x - cx, dy = y - cy, dz = z - cz;
+    const float dx = x - c[0], dy = y - c[1], dz = z - c[2];
     float d2 = dx * dx;
     d2 = d2 + dy * dy;
     d2 = d2 + dz * dz;
-    return level_of_distance(sqrtf(d2), d_near, d_far, nmin, nmax);
+    return sqrtf(d2);
+}
+
+// The distance range of camera c of a scene: given, or found this step
+// (min, max over the particles; [0, 0] when nothing was found)
+__device__ __forceinline__ void camera_range(const SceneDev &S, const uint32_t *__restrict__ range, int c,
+                                             float &d_near, float &d_far)
+{
+    if (S.auto_range) {
+        d_near = __uint_as_float(range[S.range_off + 2 * c]);
+        d_far = __uint_as_float(range[S.range_off + 2 * c + 1]);
+        if (d_far < d_near) d_near = d_far = 0.f;
+    } else {
+        d_near = S.rng[c][0];
+        d_far = S.rng[c][1];
+    }
+}
+
+// Distance-to-camera level (DTC): the highest level over the scene's cameras
+__device__ __forceinline__ int dtc_level(const SceneDev &S, const uint32_t *__restrict__ range, float x,
+                                         float y, float z)
+{
+    int L = 0;
+    for (int c = 0; c < S.n_cam; ++c) {
+        float dn, df;
+        camera_range(S, range, c, dn, df);
+        L = max(L, level_of_distance(camera_distance(x, y, z, S.cams[c]), dn, df, S.n_min, S.n_max));
+    }
+    return L;
 }
 
 // Pinhole projection for the distance-to-the-visible-surface model (DTVS):
@@ -168,17 +197,80 @@ __device__ __forceinline__ bool dtvs_project(const SceneDev &S, float x, float y
     return true;
 }
 
-// DTVS level: the particle's distance to the camera minus the depth of the
-// visible surface at its pixel; the lowest level when it is not seen
-__device__ __forceinline__ int dtvs_level(const SceneDev &S, const uint32_t *__restrict__ depth,
-                                          float x, float y, float z)
+// DTVS distance: the particle's distance to the camera minus the depth of
+// the visible surface at its pixel; false when it is not seen
+__device__ __forceinline__ bool dtvs_distance(const SceneDev &S, const uint32_t *__restrict__ depth,
+                                              float x, float y, float z, float &d)
 {
 #pragma clang fp contract(off)
     Proj o;
-    float d = 3.402823466e38f;  // largest float: lowest level
-    if (dtvs_project(S, x, y, z, o) && o.pu >= 0 && o.pu < S.img_w && o.pv >= 0 && o.pv < S.img_h)
-        d = o.dist - __uint_as_float(depth[S.depth_off + (uint32_t)o.pv * (uint32_t)S.img_w + (uint32_t)o.pu]);
-    return level_of_distance(d, S.d_near, S.d_far, S.n_min, S.n_max);
+    if (!(dtvs_project(S, x, y, z, o) && o.pu >= 0 && o.pu < S.img_w && o.pv >= 0 && o.pv < S.img_h))
+        return false;
+    d = o.dist - __uint_as_float(depth[S.depth_off + (uint32_t)o.pv * (uint32_t)S.img_w + (uint32_t)o.pu]);
+    return true;
+}
+
+// DTVS level; the lowest level when the particle is not seen
+__device__ __forceinline__ int dtvs_level(const SceneDev &S, const uint32_t *__restrict__ depth,
+                                          const uint32_t *__restrict__ range, float x, float y, float z)
+{
+    float d;
+    if (!dtvs_distance(S, depth, x, y, z, d)) d = 3.402823466e38f;  // largest float
+    float dn, df;
+    camera_range(S, range, 0, dn, df);
+    return level_of_distance(d, dn, df, S.n_min, S.n_max);
+}
+
+// Automatic distance ranges (Section 4.1): clear to (+infinity, 0), then
+// every particle of such a scene lowers the minimum and raises the maximum
+// of each of its cameras' distances (unsigned order of the float bits, which
+// orders non-negative floats; order-independent).  A wave whose particles
+// all belong to one scene combines its values first.
+__global__ void k_range_clear(uint32_t m, uint32_t *__restrict__ range)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) range[e] = (e & 1u) ? 0u : 0x7f800000u;
+}
+
+__global__ void k_lod_range(int64_t n, const SceneDev *__restrict__ sc, const float4 *__restrict__ x,
+                            const uint32_t *__restrict__ depth, uint32_t *__restrict__ range)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = s < n;
+    const float4 xi = valid ? x[s] : make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+    const int scene = __float_as_int(xi.w);
+    const SceneDev &S = sc[scene];
+    const bool on = valid && S.auto_range && (S.lod_mode == PBF_LOD_DTC || S.lod_mode == PBF_LOD_DTVS);
+    // one scene for the whole wave (lanes past the end count as that scene)
+    const int first = __shfl(scene, 0, 64);
+    const bool uniform = __all(!valid || scene == first);
+    const int ncam = on ? (S.lod_mode == PBF_LOD_DTC ? S.n_cam : 1) : 0;
+    const int nloop = uniform ? __shfl(ncam, 0, 64) : ncam;
+    for (int c = 0; c < nloop; ++c) {
+        float lo = __uint_as_float(0x7f800000u), hi = 0.f;
+        if (on && c < ncam) {
+            float d;
+            bool seen = true;
+            if (S.lod_mode == PBF_LOD_DTC) d = camera_distance(xi.x, xi.y, xi.z, S.cams[c]);
+            else seen = dtvs_distance(S, depth, xi.x, xi.y, xi.z, d);
+            if (seen) lo = hi = d;
+        }
+        if (uniform) {
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = fminf(lo, __shfl_xor(lo, o, 64));
+                hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+            }
+            if ((threadIdx.x & 63) != 0) continue;
+            if (!(sc[first].auto_range)) continue;
+        } else if (!(on && c < ncam)) {
+            continue;
+        }
+        const SceneDev &T = uniform ? sc[first] : S;
+        uint32_t *w = &range[T.range_off + 2 * c];
+        const uint32_t bl = __float_as_uint(lo), bh = __float_as_uint(hi);
+        if (bl < w[0]) atomicMin(&w[0], bl);  // values only move outwards: a stale read is safe
+        if (bh > w[1]) atomicMax(&w[1], bh);
+    }
 }
 
 // Depth images of the DTVS scenes: clear to +infinity, then every particle
@@ -245,7 +337,7 @@ __device__ __forceinline__ uint32_t cell_ticket(uint32_t k, bool valid, uint32_t
 __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
                               const float4 *__restrict__ x, float4 *__restrict__ v,
                               const uint32_t *__restrict__ id, const uint8_t *__restrict__ lev_by_id,
-                              const uint32_t *__restrict__ depth,
+                              const uint32_t *__restrict__ depth, const uint32_t *__restrict__ range,
                               float4 *__restrict__ xs_pred, uint8_t *__restrict__ lvl,
                               uint32_t *__restrict__ key, uint32_t *__restrict__ ticket,
                               uint32_t *__restrict__ cell_count,
@@ -264,10 +356,9 @@ __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
         if (S.lod_mode == PBF_LOD_EXPLICIT) {
             L = lev_by_id[id[s]];
         } else if (S.lod_mode == PBF_LOD_DTC) {
-            L = dtc_level(xi.x, xi.y, xi.z, S.cam[0], S.cam[1], S.cam[2], S.d_near, S.d_far,
-                          nmin, nmax);
+            L = dtc_level(S, range, xi.x, xi.y, xi.z);
         } else if (S.lod_mode == PBF_LOD_DTVS) {
-            L = dtvs_level(S, depth, xi.x, xi.y, xi.z);
+            L = dtvs_level(S, depth, range, xi.x, xi.y, xi.z);
         } else {
             L = nmax;
         }
@@ -1092,7 +1183,7 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
                                             uint32_t nown, uint32_t first, uint32_t last)
 {
     const float h = S.h, h2 = S.h2, cg = S.c_grad, h6 = S.h6, crho = S.c_rho, cs = S.c_s,
-                eps = S.eps;
+                eps = S.eps, cfloor = S.c_floor;
     for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
         const size_t p = p0 + pl;
         const uint32_t meta = pmeta[p];
@@ -1114,7 +1205,7 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
             gz += q * dz;
             g2 += q * q * r2;
         });
-        const float C = crho * sum6 - 1.f;
+        const float C = fmaxf(crho * sum6 - 1.f, cfloor);  // unilateral: C >= 0
         const float denom = cs * cg * cg * (gx * gx + gy * gy + gz * gz + g2) + eps;
         xs[i].w = -C / denom;
     }
@@ -1465,10 +1556,15 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
         LAUNCH(K_DEPTH, blocks_for(b.n_depth, 256), 256, k_depth_clear, b.n_depth, b.depth);
         LAUNCH(K_DEPTH, blocks_for(n, 256), 256, k_depth_splat, n, b.scenes, b.x[cur], b.depth);
     }
+    if (b.n_range) {  // automatic distance ranges
+        LAUNCH(K_LOD_RANGE, blocks_for(b.n_range, 256), 256, k_range_clear, b.n_range, b.range);
+        LAUNCH(K_LOD_RANGE, blocks_for(n, bs[K_LOD_RANGE]), bs[K_LOD_RANGE], k_lod_range, n, b.scenes,
+               b.x[cur], b.depth, b.range);
+    }
     // cell_count is all zero here: cleared at creation, and by the cell scan
     // of every step once it has read the counts
     LAUNCH(K_LOD_PREDICT, blocks_for(n, bs[K_LOD_PREDICT]), bs[K_LOD_PREDICT], k_lod_predict, n,
-           b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.depth, b.xs_pred, b.lvl[cur],
+           b.scenes, b.x[cur], b.v[cur], b.id[cur], b.lev_by_id, b.depth, b.range, b.xs_pred, b.lvl[cur],
            b.key_pre, b.ticket, b.cell_count, b.level_part);
     if ((e = enqueue_scan(b.cell_count, G, b.scan_part, b.cell_start, true, s, tm)) != hipSuccess)
         return e;

@@ -73,7 +73,7 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [
     dict(n=-1), dict(n_min=0), dict(n_min=5, n_max=4), dict(n_max=33), dict(h=0.0),
     dict(h=float("nan")), dict(rho0=-1.0), dict(mass=0.0), dict(eps=-1.0), dict(dt=0.0),
-    dict(box_hi=(1.0, -1.0, 1.0)), dict(grid_dims=(4, -1, 4)), dict(flags=1),
+    dict(box_hi=(1.0, -1.0, 1.0)), dict(grid_dims=(4, -1, 4)), dict(flags=2),
     dict(max_neighbours=-3), dict(gravity=(0.0, float("inf"), 0.0)),
 ])
 def test_invalid_params_rejected_on_host(lib, bad):
