@@ -300,6 +300,80 @@ def run_rollout(args, torch, stream):
     }
 
 
+def run_multidam(args, torch, stream):
+    """The multi-dam-break scene of Section 7.3: four blocks of 35 x 46 x 35
+    particles (225,400 in all) in the corners of a 6.4 x 3.2 x 6.4 box around
+    a solid cone (base radius 1.5, height 2.0) standing at its centre;
+    distance-to-camera levels N_i in {4..8}, one pre-stabilisation iteration
+    for N_i < 6, dt = 1/120.  The first 60 steps (untimed) bring the fluid
+    onto the cone; the timed steps follow.  Against plain PBF with N = 8 and
+    N = 4 and against APBF without the cone, from the same state."""
+    import dataclasses
+
+    import scenes
+    from paper_1608_04721_amd import PBF_LOD_UNIFORM, PbfError, Sim
+
+    sc = scenes.multi_dam_break()
+    warm = max(args.warmup, 60)
+    runs = {}
+    # plain PBF: every N_i = N, so the pre-stabilised set N_i < S is empty
+    variants = [("apbf", sc),
+                ("pbf8", dataclasses.replace(sc.with_lod(PBF_LOD_UNIFORM, n_min=8, n_max=8), stab_s=1)),
+                ("pbf4", dataclasses.replace(sc.with_lod(PBF_LOD_UNIFORM, n_min=4, n_max=4), stab_s=1)),
+                ("apbf_no_cone", dataclasses.replace(sc, obstacles=(), stab_iters=0, stab_s=1))]
+    for name, s in variants:
+        print(f"[bench] multidam {name}", file=sys.stderr, flush=True)
+        with Sim(s, stream=stream, max_neighbours=128) as sim:
+            try:
+                runs[name] = _timed_run(sim, args.steps, warm, stream, torch)
+                runs[name]["contacts_last_step"] = int(np.count_nonzero(sim.debug_contacts()))
+            except PbfError as e:
+                runs[name] = {"error": str(e)}
+    # per-kernel times over a few direct-launch steps from the warmed state
+    with Sim(sc, stream=stream, max_neighbours=128) as sim:
+        sim.set_graph(True)
+        sim.step(warm)
+        sim.sync()
+        sim.set_graph(False)
+        sim.profile_enable(True)
+        sim.step(args.profile_steps)
+        prof = sim.profile_read()
+    kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1],
+                   "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
+               for k, v in prof.items() if v[1]}
+    a = runs["apbf"]
+
+    def short(r):
+        if "error" in r:
+            return r
+        return {"ms_per_step": round(r["ms_per_step"], 4), "value": round(r["value"], 1),
+                "mean_levels": round(r["mean_levels"], 4), "density": r["density"],
+                "contacts_last_step": r["contacts_last_step"]}
+
+    line = {
+        "metric": "particle-iterations/s and ms/step, multi dam break with a central cone, "
+                  "APBF vs PBF(N=8)",
+        "value": round(a["value"], 1), "unit": "particle-iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": warm, "ms_per_step": round(a["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "multi_dam_break: 4 blocks of 35x46x35 particles (225,400), box "
+                               "6.4x3.2x6.4, solid cone r=1.5 h=2.0 at the centre, "
+                               "distance-to-camera levels 4..8, pre-stabilisation 1 iteration "
+                               "for N_i < 6, dt=1/120, timed after 60 steps",
+                   "particles": sc.n, "levels": [sc.n_min, sc.n_max],
+                   "launch": "hipGraph per step"},
+        "ms_median": round(a["ms_median"], 4), "mean_levels": round(a["mean_levels"], 4),
+        "density": a["density"], "contacts_last_step": a["contacts_last_step"],
+        "pbf": {"8": short(runs["pbf8"]), "4": short(runs["pbf4"])},
+        "apbf_no_cone": short(runs["apbf_no_cone"]),
+        "kernels": kernels,
+    }
+    if "error" not in runs["pbf8"]:
+        line["speedup_vs_pbf8"] = round(runs["pbf8"]["ms_per_step"] / a["ms_per_step"], 4)
+    return line
+
+
 def run_traffic(args, torch, stream):
     """A short run for hardware-counter passes (rocprofv3 --pmc FETCH_SIZE,
     then WRITE_SIZE): first a plain device copy of 256 MiB, three times,
@@ -331,9 +405,11 @@ def run_traffic(args, torch, stream):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--workload", choices=("tank", "batch", "rollout", "traffic"), default="tank",
+    ap.add_argument("--workload", choices=("tank", "batch", "rollout", "multidam", "traffic"),
+                    default="tank",
                     help="tank: the 1M-particle headline line (default); batch: 64 scenes; "
-                         "rollout: reverse-mode cost on the 32k-particle rollout; traffic: "
+                         "rollout: reverse-mode cost on the 32k-particle rollout; multidam: "
+                         "four dam breaks around a solid cone with pre-stabilisation; traffic: "
                          "short run for hardware-counter passes")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
@@ -364,6 +440,9 @@ def main(argv=None):
         return 0
     if args.workload == "traffic":
         print(json.dumps(run_traffic(args, torch, stream)), flush=True)
+        return 0
+    if args.workload == "multidam":
+        print(json.dumps(run_multidam(args, torch, stream)), flush=True)
         return 0
     sc = scenes.tank_1m()
     steps, warm = args.steps, args.warmup
