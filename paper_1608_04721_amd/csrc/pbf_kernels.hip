@@ -1132,13 +1132,12 @@ __device__ __forceinline__ void for_each_neighbour(const TileTables &tb,
                                                    const float4 *__restrict__ stage,
                                                    const float4 *__restrict__ src,
                                                    const uint4 *__restrict__ nbr, int64_t n,
-                                                   size_t p, uint32_t cnt, F &&f)
+                                                   size_t p, uint32_t cnt, uint4 v, F &&f)
 {
-    // the next group's codes are loaded while this group is evaluated; the
-    // index is clamped to the last group (group 0 exists for every p), so
-    // every load is unconditional
+    // v holds group 0 (loaded by the caller); the next group's codes are
+    // loaded while this group is evaluated; the index is clamped to the last
+    // group (group 0 exists for every p), so every load is unconditional
     const uint32_t last = cnt ? (cnt - 1u) >> 3 : 0u;
-    uint4 v = nbr[p];
     for (uint32_t q = 0; q < cnt; q += 8) {
         const uint4 vn = nbr[(size_t)min((q >> 3) + 1u, last) * n + p];
         const uint32_t cc[8] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16,
@@ -1173,6 +1172,28 @@ __device__ __forceinline__ void for_each_neighbour(const TileTables &tb,
 // once per particle instead of once per pair.
 constexpr float kTinyR2 = 1e-20f;
 
+// A thread's first own particle: its metadata, slot and first code group,
+// loaded before the tile's stage so that they arrive while it is staged.
+struct Head {
+    uint32_t meta, slot;
+    uint4 g0;
+};
+
+__device__ __forceinline__ Head load_head(const uint32_t *__restrict__ pmeta,
+                                          const uint32_t *__restrict__ pslot,
+                                          const uint4 *__restrict__ nbr, uint32_t p0, uint32_t first,
+                                          uint32_t last)
+{
+    Head hd{0u, 0u, make_uint4(0u, 0u, 0u, 0u)};
+    const uint32_t pl = first + threadIdx.x;
+    if (pl < last) {
+        hd.meta = pmeta[p0 + pl];
+        hd.slot = pslot[p0 + pl];
+        hd.g0 = nbr[p0 + pl];
+    }
+    return hd;
+}
+
 // lambda_i for the active own particles of a tile (Eqs. 4-6)
 template <bool FITS>
 __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const TileTables &tb,
@@ -1180,19 +1201,22 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
                                             int64_t n, const uint4 *__restrict__ nbr,
                                             const uint32_t *__restrict__ pmeta,
                                             const uint32_t *__restrict__ pslot, uint32_t p0,
-                                            uint32_t nown, uint32_t first, uint32_t last)
+                                            uint32_t nown, uint32_t first, uint32_t last,
+                                            const Head &hd)
 {
     const float h = S.h, h2 = S.h2, cg = S.c_grad, h6 = S.h6, crho = S.c_rho, cs = S.c_s,
                 eps = S.eps, cfloor = S.c_floor;
     for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
+        const bool head = pl == first + threadIdx.x;
         const size_t p = p0 + pl;
-        const uint32_t meta = pmeta[p];
-        const uint32_t i = pslot[p];  // independent loads, issued together
+        const uint32_t meta = head ? hd.meta : pmeta[p];
+        const uint32_t i = head ? hd.slot : pslot[p];  // independent loads, issued together
         if ((int)meta_level(meta) <= k) continue;
         const float4 xi = FITS ? stage[meta_self(meta)] : xs[i];
         float sum6 = h6;  // the particle itself: (h^2 - 0)^3
         float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
-        for_each_neighbour<FITS>(tb, stage, xs, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+        for_each_neighbour<FITS>(tb, stage, xs, nbr, n, p, meta & kMetaCount, head ? hd.g0 : nbr[p],
+                                 [&](const float4 &xj) {
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float w = fmaxf(h2 - r2, 0.f);
@@ -1231,10 +1255,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
+    const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
     if (stage_rows(rows, tile, xs, tb, stage))
-        tile_lambda<true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last);
+        tile_lambda<true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
     else
-        tile_lambda<false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last);
+        tile_lambda<false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
 }
 
 // Delta p_i (Eq. 7) with the wall contact (clamp) for the active own
@@ -1248,15 +1273,17 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
                                             const uint32_t *__restrict__ pmeta,
                                             const uint32_t *__restrict__ pslot,
                                             const uint8_t *__restrict__ contact, uint32_t p0,
-                                            uint32_t nown, uint32_t first, uint32_t last)
+                                            uint32_t nown, uint32_t first, uint32_t last,
+                                            const Head &hd)
 {
     const float h = S.h, cg = S.c_grad, sr = S.inv_rho0;
     const float lo0 = S.lo[0], lo1 = S.lo[1], lo2 = S.lo[2];
     const float hi0 = S.hi[0], hi1 = S.hi[1], hi2 = S.hi[2];
     for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
+        const bool head = pl == first + threadIdx.x;
         const size_t p = p0 + pl;
-        const uint32_t meta = pmeta[p];
-        const uint32_t i = pslot[p];  // independent loads, issued together
+        const uint32_t meta = head ? hd.meta : pmeta[p];
+        const uint32_t i = head ? hd.slot : pslot[p];  // independent loads, issued together
         const int L = (int)meta_level(meta);
         if (L < k) continue;
         const float4 xi = FITS ? stage[meta_self(meta)] : xs_in[i];
@@ -1266,7 +1293,8 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
         }
         const float li = xi.w;
         float px = 0.f, py = 0.f, pz = 0.f;
-        for_each_neighbour<FITS>(tb, stage, xs_in, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+        for_each_neighbour<FITS>(tb, stage, xs_in, nbr, n, p, meta & kMetaCount, head ? hd.g0 : nbr[p],
+                                 [&](const float4 &xj) {
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, kTinyR2));
@@ -1309,12 +1337,13 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
+    const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
     if (stage_rows(rows, tile, xs_in, tb, stage))
         tile_update<true, CONTACTS>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact, p0,
-                                    nown, first, last);
+                                    nown, first, last, hd);
     else
         tile_update<false, CONTACTS>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact, p0,
-                                     nown, first, last);
+                                     nown, first, last, hd);
 }
 
 // ------------------------------------------------ average density
@@ -1365,7 +1394,7 @@ __device__ __forceinline__ void tile_density(const SceneDev &S, const TileTables
         const uint32_t i = pslot[p];
         const float4 xi = FITS ? stage[meta_self(meta)] : x[i];
         float sum6 = h6;
-        for_each_neighbour<FITS>(tb, stage, x, nbr, n, p, meta & kMetaCount, [&](const float4 &xj) {
+        for_each_neighbour<FITS>(tb, stage, x, nbr, n, p, meta & kMetaCount, nbr[p], [&](const float4 &xj) {
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float w = fmaxf(h2 - (dx * dx + dy * dy + dz * dz), 0.f);
             sum6 += w * w * w;
