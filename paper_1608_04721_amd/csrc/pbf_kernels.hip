@@ -989,21 +989,16 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         const float4 xi = FITS ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
         const size_t p = p0 + pl;
         uint32_t cnt = 0;
-        uint64_t acc = 0, half = 0;  // codes cnt & ~3 .. cnt - 1; first half of the group
         const uint32_t cap8 = ((uint32_t)cap + 7u) & ~7u;  // codes that have room
+        // each code is stored as it is found, 16 bits at a time; the pointer
+        // steps one code inside a group and on to the particle's next group
+        // (n groups further) after the eighth code
+        uint16_t *__restrict__ w = reinterpret_cast<uint16_t *>(nbr + p);
+        const int64_t jump = 8 * n - 7;
         auto put = [&](uint32_t code) {
-            acc |= (uint64_t)code << ((cnt & 3u) * 16u);
+            if (cnt < cap8) *w = (uint16_t)code;
             ++cnt;
-            if ((cnt & 3u) == 0) {
-                if (cnt & 4u) {
-                    half = acc;
-                } else if (cnt <= cap8) {
-                    nbr[(size_t)((cnt >> 3) - 1) * n + p] =
-                        make_uint4((uint32_t)half, (uint32_t)(half >> 32), (uint32_t)acc,
-                                   (uint32_t)(acc >> 32));
-                }
-                acc = 0;
-            }
+            w += (cnt & 7u) ? (int64_t)1 : jump;
         };
 #pragma unroll 1
         for (int w = 0; w < 9; ++w) {
@@ -1050,15 +1045,9 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         if (cnt > (uint32_t)cap) {
             bad |= ERR_NEIGHBOUR_CAP;
             cnt = (uint32_t)cap & ~7u;  // only whole stored groups are valid
-        } else if (cnt & 7u) {
+        } else if (FITS && (cnt & 7u)) {
             const uint32_t keep = cnt;
-            if (FITS) {
-                while (cnt & 7u) put(kFarCode);  // pad; stores the group
-            } else {
-                const uint64_t lo = (cnt & 4u) ? half : acc, hi = (cnt & 4u) ? acc : 0;
-                nbr[(size_t)(cnt >> 3) * n + p] =
-                    make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
-            }
+            while (cnt & 7u) put(kFarCode);  // pad the last group (the HBM path reads only cnt codes)
             cnt = keep;
         }
         pslot[p] = i;
