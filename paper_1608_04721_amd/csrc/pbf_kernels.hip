@@ -1184,7 +1184,7 @@ __device__ __forceinline__ Head load_head(const uint32_t *__restrict__ pmeta,
 }
 
 // lambda_i for the active own particles of a tile (Eqs. 4-6)
-template <bool FITS>
+template <bool FITS, bool WIDE>
 __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const TileTables &tb,
                                             const float4 *__restrict__ stage, float4 *__restrict__ xs,
                                             int64_t n, const uint4 *__restrict__ nbr,
@@ -1206,6 +1206,10 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
         float gx = 0.f, gy = 0.f, gz = 0.f, g2 = 0.f;
         for_each_neighbour<FITS>(tb, stage, xs, nbr, n, p, meta & kMetaCount, head ? hd.g0 : nbr[p],
                                  [&](const float4 &xj) {
+            // keep the 16-byte LDS read (an empty asm that takes .w): on
+            // gfx950 random 12-byte reads conflict more than 16-byte ones
+            // (measured 4% on this pass); the split variant would spill
+            if (WIDE) asm volatile("" : : "v"(xj.w));
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float w = fmaxf(h2 - r2, 0.f);
@@ -1246,9 +1250,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
     if (stage_rows(rows, tile, xs, tb, stage))
-        tile_lambda<true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
+        tile_lambda<true, !SPLIT>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
     else
-        tile_lambda<false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
+        tile_lambda<false, !SPLIT>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
 }
 
 // Delta p_i (Eq. 7) with the wall contact (clamp) for the active own
