@@ -1021,6 +1021,7 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                     uint32_t nib = 0;  // hits of the four, bit u
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
+                        if (FITS) asm volatile("" : : "v"(xj[u].w));  // 16-byte LDS reads
                         const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
                         nib |= (dx * dx + dy * dy + dz * dz < h2) ? (1u << u) : 0u;
                     }
