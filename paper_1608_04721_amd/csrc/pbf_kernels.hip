@@ -283,27 +283,86 @@ __global__ void k_depth_clear(uint32_t m, uint32_t *__restrict__ depth)
     if (e < m) depth[e] = 0x7f800000u;
 }
 
-__global__ void k_depth_splat(int64_t n, const SceneDev *__restrict__ sc,
-                              const float4 *__restrict__ x, uint32_t *__restrict__ depth)
+constexpr int kSplatThreads = 256;  // particles per splat workgroup
+constexpr int kSplatTile = 4096;    // pixels of a workgroup's LDS depth tile (16 KB)
+
+__global__ __launch_bounds__(kSplatThreads) void k_depth_splat(int64_t n, const SceneDev *__restrict__ sc,
+                                                             const float4 *__restrict__ x,
+                                                             uint32_t *__restrict__ depth)
 {
+    // Consecutive particles (cell order) splat overlapping squares, about
+    // five per pixel for a workgroup.  Their minimum is taken in an LDS tile
+    // over the workgroup's bounding box first, so the depth image gets one
+    // read (and at most one atomic) per pixel the workgroup touches; a
+    // workgroup spanning scenes or a box larger than the tile writes each
+    // particle's square to the image directly.
+    __shared__ uint32_t img[kSplatTile];
+    __shared__ int box[6];  // a0, b0, -a1, -b1 (minima), smallest and largest scene
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const float4 xi = x[s];
-    const SceneDev &S = sc[__float_as_int(xi.w)];
-    if (S.lod_mode != PBF_LOD_DTVS) return;
-    Proj o;
-    if (!dtvs_project(S, xi.x, xi.y, xi.z, o)) return;
-    const uint32_t bits = __float_as_uint(o.dist);
-    const int a0 = max(o.pu - o.rad, 0), a1 = min(o.pu + o.rad, S.img_w - 1);
-    const int b0 = max(o.pv - o.rad, 0), b1 = min(o.pv + o.rad, S.img_h - 1);
-    // the particles along one ray all land on the same pixels: a plain read
-    // first, and an atomic only where it can still lower the value (a stale
-    // read costs one needless atomic; the minimum is the same either way)
-    for (int b = b0; b <= b1; ++b)
-        for (int a = a0; a <= a1; ++a) {
-            uint32_t *px = &depth[S.depth_off + (uint32_t)b * (uint32_t)S.img_w + (uint32_t)a];
-            if (bits < *px) atomicMin(px, bits);  // values only fall: a stale read is safe
+    if (threadIdx.x == 0) {
+        box[0] = box[1] = box[2] = box[3] = INT_MAX;
+        box[4] = INT_MAX;
+        box[5] = -1;
+    }
+    __syncthreads();
+    bool ok = false;
+    int scene = 0, a0 = 0, a1 = -1, b0 = 0, b1 = -1;
+    uint32_t bits = 0;
+    if (s < n) {
+        const float4 xi = x[s];
+        scene = __float_as_int(xi.w);
+        const SceneDev &S = sc[scene];
+        Proj o;
+        if (S.lod_mode == PBF_LOD_DTVS && dtvs_project(S, xi.x, xi.y, xi.z, o)) {
+            bits = __float_as_uint(o.dist);
+            a0 = max(o.pu - o.rad, 0);
+            a1 = min(o.pu + o.rad, S.img_w - 1);
+            b0 = max(o.pv - o.rad, 0);
+            b1 = min(o.pv + o.rad, S.img_h - 1);
+            ok = a0 <= a1 && b0 <= b1;
         }
+    }
+    if (ok) {
+        atomicMin(&box[0], a0);
+        atomicMin(&box[1], b0);
+        atomicMin(&box[2], -a1);
+        atomicMin(&box[3], -b1);
+        atomicMin(&box[4], scene);
+        atomicMax(&box[5], scene);
+    }
+    __syncthreads();
+    const int x0 = box[0], y0 = box[1], bw = -box[2] - x0 + 1, bh = -box[3] - y0 + 1;
+    const bool any = box[5] >= 0;
+    const bool tiled = any && box[4] == box[5] && (int64_t)bw * bh <= kSplatTile;  // uniform
+    if (!tiled) {
+        // the particles along one ray all land on the same pixels: a plain
+        // read first, and an atomic only where it can still lower the value
+        // (a stale read costs one needless atomic; the minimum is the same)
+        if (ok) {
+            const SceneDev &S = sc[scene];
+            for (int b = b0; b <= b1; ++b)
+                for (int a = a0; a <= a1; ++a) {
+                    uint32_t *px = &depth[S.depth_off + (uint32_t)b * (uint32_t)S.img_w + (uint32_t)a];
+                    if (bits < *px) atomicMin(px, bits);  // values only fall: a stale read is safe
+                }
+        }
+        return;
+    }
+    const int m = bw * bh;
+    for (int e = threadIdx.x; e < m; e += blockDim.x) img[e] = 0x7f800000u;
+    __syncthreads();
+    if (ok)
+        for (int b = b0; b <= b1; ++b)
+            for (int a = a0; a <= a1; ++a) atomicMin(&img[(b - y0) * bw + (a - x0)], bits);
+    __syncthreads();
+    const SceneDev &T = sc[box[4]];
+    for (int e = threadIdx.x; e < m; e += blockDim.x) {
+        const uint32_t v = img[e];
+        if (v == 0x7f800000u) continue;
+        const int r = e / bw, c = e - r * bw;
+        uint32_t *px = &depth[T.depth_off + (uint32_t)(y0 + r) * (uint32_t)T.img_w + (uint32_t)(x0 + c)];
+        if (v < *px) atomicMin(px, v);
+    }
 }
 
 // Ticket of a particle inside its cell from the counting-sort histogram (all
@@ -1577,7 +1636,8 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
 
     if (b.n_depth) {  // depth images of the distance-to-the-visible-surface scenes
         LAUNCH(K_DEPTH, blocks_for(b.n_depth, 256), 256, k_depth_clear, b.n_depth, b.depth);
-        LAUNCH(K_DEPTH, blocks_for(n, 256), 256, k_depth_splat, n, b.scenes, b.x[cur], b.depth);
+        LAUNCH(K_DEPTH, blocks_for(n, kSplatThreads), kSplatThreads, k_depth_splat, n, b.scenes, b.x[cur],
+               b.depth);
     }
     if (b.n_range) {  // automatic distance ranges
         LAUNCH(K_LOD_RANGE, blocks_for(b.n_range, 256), 256, k_range_clear, b.n_range, b.range);
