@@ -117,6 +117,30 @@ def test_random_levels(seed):
             assert st["active"][k] == int((info["levels"] > k).sum())
 
 
+def test_maximum_level_count():
+    # levels spread over the whole range 1..PBF_MAX_ITERS (32 iterations).
+    # Thirty-two Jacobi iterations of this free-surface block are ill
+    # conditioned: a one-ulp change of the input moves the oracle's own
+    # result by ~1e-2 (16 iterations: 6e-6), so positions get 4x the
+    # measured spread; keys, levels, neighbours and active counts stay exact.
+    from paper_1608_04721_amd import PBF_MAX_ITERS
+    sc = scenes.block(11, 10, 9, seed=4, n_min=1, n_max=PBF_MAX_ITERS, levels="random",
+                      vel_sigma=0.3)
+    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+    assert info["levels"].max() == PBF_MAX_ITERS and info["levels"].min() == 1
+    sens_x, sens_l = ulp_sensitivity(sc)
+    tol = max(pos_tol(sc), 4.0 * sens_x)
+    print(f"one-ulp spread of the oracle {sens_x:.2e}, tolerance {tol:.2e}")
+    with _sim(sc) as sim:
+        sim.set_graph(True)
+        sim.step(1)
+        _check_step(sc, sim, x_ref, v_ref, info, tol=tol, lam_extra=4.0 * sens_l)
+        st = sim.stats()
+        assert st["n_iters"] == PBF_MAX_ITERS
+        for k in range(PBF_MAX_ITERS):
+            assert st["active"][k] == int((info["levels"] > k).sum())
+
+
 def test_distance_to_camera_levels():
     sc = scenes.block(16, 8, 16, seed=5, n_min=3, n_max=8, vel_sigma=0.2)
     cam = np.array([0.4, 1.0, -0.8], np.float32)
