@@ -394,7 +394,7 @@ __device__ __forceinline__ uint32_t cell_ticket(uint32_t k, bool valid, uint32_t
 // key of x*, and a ticket inside its cell from the counting-sort histogram.
 // Lanes of a wave that share a cell take one atomic for all of them.
 __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
-                              const float4 *__restrict__ x, float4 *__restrict__ v,
+                              const float4 *__restrict__ x, const float4 *__restrict__ v,
                               const uint32_t *__restrict__ id, const uint8_t *__restrict__ lev_by_id,
                               const uint32_t *__restrict__ depth, const uint32_t *__restrict__ range,
                               float4 *__restrict__ xs_pred, uint8_t *__restrict__ lvl,
@@ -422,14 +422,13 @@ __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
             L = nmax;
         }
         const float dt = S.dt;
-        float4 vi = v[s];
+        float4 vi = v[s];  // v + dt g is only needed for x*: the commit recomputes v
         vi.x += dt * S.g[0];
         vi.y += dt * S.g[1];
         vi.z += dt * S.g[2];
         const float px = clampf(xi.x + dt * vi.x, S.lo[0], S.hi[0]);
         const float py = clampf(xi.y + dt * vi.y, S.lo[1], S.hi[1]);
         const float pz = clampf(xi.z + dt * vi.z, S.lo[2], S.hi[2]);
-        v[s] = vi;
         xs_pred[s] = make_float4(px, py, pz, 0.f);
         lvl[s] = (uint8_t)L;
         const float h = S.h;
@@ -536,14 +535,14 @@ __global__ void k_sort_scatter(int64_t n, const uint32_t *__restrict__ key,
 
 // Final slot = cell start + rank of the particle ID inside its cell (ties of
 // the counting sort in particle-ID order), then move the particle there.
+// Velocities are not moved: the commit recomputes every one from x and x*.
 __global__ void k_sort_finish(int64_t n, const uint32_t *__restrict__ tmp_src,
                               const uint32_t *__restrict__ tmp_id,
                               const uint32_t *__restrict__ key_pre,
                               const uint32_t *__restrict__ cell_start,
-                              const float4 *__restrict__ x, const float4 *__restrict__ v,
-                              const float4 *__restrict__ xs_pred,
+                              const float4 *__restrict__ x, const float4 *__restrict__ xs_pred,
                               const uint8_t *__restrict__ lvl_in, float4 *__restrict__ x_out,
-                              float4 *__restrict__ v_out, float4 *__restrict__ xs_out,
+                              float4 *__restrict__ xs_out,
                               uint32_t *__restrict__ id_out, uint8_t *__restrict__ lvl_out,
                               uint32_t *__restrict__ key_out, uint32_t *__restrict__ err)
 {
@@ -563,7 +562,6 @@ __global__ void k_sort_finish(int64_t n, const uint32_t *__restrict__ tmp_src,
         f = lo + r;
     }
     x_out[f] = x[s];
-    v_out[f] = v[s];
     xs_out[f] = xs_pred[s];
     id_out[f] = my;
     lvl_out[f] = lvl_in[s];
@@ -1654,8 +1652,8 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     LAUNCH(K_SORT_SCATTER, blocks_for(n, bs[K_SORT_SCATTER]), bs[K_SORT_SCATTER], k_sort_scatter,
            n, b.key_pre, b.ticket, b.cell_start, b.id[cur], b.tmp_src, b.tmp_id);
     LAUNCH(K_SORT_FINISH, blocks_for(n, bs[K_SORT_FINISH]), bs[K_SORT_FINISH], k_sort_finish, n,
-           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.v[cur], b.xs_pred,
-           b.lvl[cur], b.x[nxt], b.v[nxt], b.xs[0], b.id[nxt], b.lvl[nxt], b.key, b.err);
+           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.xs_pred, b.lvl[cur],
+           b.x[nxt], b.xs[0], b.id[nxt], b.lvl[nxt], b.key, b.err);
     // tiles: own counts and levels, their prefix, and the level buckets
     LAUNCH(K_TILE_PREPARE, blocks_for((int64_t)T * 64, bs[K_TILE_PREPARE]), bs[K_TILE_PREPARE],
            k_tile_prepare, T, b.scenes, b.tile_scene, b.cell_start, b.lvl[nxt], b.tile_count,
@@ -1747,8 +1745,8 @@ hipError_t enqueue_density(const StepBuffers &b0, int cur, const LaunchShape &ls
     LAUNCH(K_SORT_SCATTER, blocks_for(n, bs[K_SORT_SCATTER]), bs[K_SORT_SCATTER], k_sort_scatter,
            n, b.key_pre, b.ticket, b.cell_start, b.id[cur], b.tmp_src, b.tmp_id);
     LAUNCH(K_SORT_FINISH, blocks_for(n, bs[K_SORT_FINISH]), bs[K_SORT_FINISH], k_sort_finish, n,
-           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.v[cur], b.xs_pred,
-           b.lvl[cur], b.x[nxt], b.v[nxt], d.xs, b.id[nxt], b.lvl[nxt], b.key, b.err);
+           b.tmp_src, b.tmp_id, b.key_pre, b.cell_start, b.x[cur], b.xs_pred, b.lvl[cur],
+           b.x[nxt], d.xs, b.id[nxt], b.lvl[nxt], b.key, b.err);
     LAUNCH(K_TILE_PREPARE, blocks_for((int64_t)T * 64, bs[K_TILE_PREPARE]), bs[K_TILE_PREPARE],
            k_tile_prepare, T, b.scenes, b.tile_scene, b.cell_start, b.lvl[nxt], b.tile_count,
            b.tile_lvl);
