@@ -283,8 +283,25 @@ __global__ void k_depth_clear(uint32_t m, uint32_t *__restrict__ depth)
     if (e < m) depth[e] = 0x7f800000u;
 }
 
+// Lower depth[idx[q]] to val[q] where on[q]: the current values are read
+// first, all together, and an atomic is issued only where it can still
+// lower the value (a stale read costs one needless atomic; the minimum is
+// the same, since values only fall)
+template <int B>
+__device__ __forceinline__ void lower_pixels(uint32_t *__restrict__ depth, const uint32_t (&idx)[B],
+                                             const uint32_t (&val)[B], const bool (&on)[B])
+{
+    uint32_t cur[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) cur[q] = on[q] ? depth[idx[q]] : 0u;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+        if (on[q] && val[q] < cur[q]) atomicMin(&depth[idx[q]], val[q]);
+}
+
 constexpr int kSplatThreads = 256;  // particles per splat workgroup
 constexpr int kSplatTile = 4096;    // pixels of a workgroup's LDS depth tile (16 KB)
+constexpr int kSplatWaves = kSplatThreads / 64;
 
 __global__ __launch_bounds__(kSplatThreads) void k_depth_splat(int64_t n, const SceneDev *__restrict__ sc,
                                                              const float4 *__restrict__ x,
@@ -295,21 +312,20 @@ __global__ __launch_bounds__(kSplatThreads) void k_depth_splat(int64_t n, const 
     // over the workgroup's bounding box first, so the depth image gets one
     // read (and at most one atomic) per pixel the workgroup touches; a
     // workgroup spanning scenes or a box larger than the tile writes each
-    // particle's square to the image directly.
-    __shared__ uint32_t img[kSplatTile];
-    __shared__ int box[6];  // a0, b0, -a1, -b1 (minima), smallest and largest scene
+    // particle's square to the image directly.  The whole tile is cleared
+    // while the positions load, and the box is combined from one entry per
+    // wave, so the workgroup waits at two barriers only.
+    __shared__ __align__(16) uint32_t img[kSplatTile];
+    __shared__ int wbox[kSplatWaves][6];  // per wave: a0, b0, -a1, -b1 (minima), scenes min, max
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (threadIdx.x == 0) {
-        box[0] = box[1] = box[2] = box[3] = INT_MAX;
-        box[4] = INT_MAX;
-        box[5] = -1;
-    }
-    __syncthreads();
+    const float4 xi = s < n ? x[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+    static_assert(kSplatTile % (4 * kSplatThreads) == 0, "tile clear");
+    for (int e = 4 * threadIdx.x; e < kSplatTile; e += 4 * kSplatThreads)
+        *reinterpret_cast<uint4 *>(&img[e]) = make_uint4(0x7f800000u, 0x7f800000u, 0x7f800000u, 0x7f800000u);
     bool ok = false;
     int scene = 0, a0 = 0, a1 = -1, b0 = 0, b1 = -1;
     uint32_t bits = 0;
     if (s < n) {
-        const float4 xi = x[s];
         scene = __float_as_int(xi.w);
         const SceneDev &S = sc[scene];
         Proj o;
@@ -322,46 +338,77 @@ __global__ __launch_bounds__(kSplatThreads) void k_depth_splat(int64_t n, const 
             ok = a0 <= a1 && b0 <= b1;
         }
     }
-    if (ok) {
-        atomicMin(&box[0], a0);
-        atomicMin(&box[1], b0);
-        atomicMin(&box[2], -a1);
-        atomicMin(&box[3], -b1);
-        atomicMin(&box[4], scene);
-        atomicMax(&box[5], scene);
+    // the wave's box by shuffles (LDS atomics of all lanes on one address
+    // would run one lane at a time), one LDS entry per wave
+    int bx[6] = {ok ? a0 : INT_MAX, ok ? b0 : INT_MAX, ok ? -a1 : INT_MAX, ok ? -b1 : INT_MAX,
+                 ok ? scene : INT_MAX, ok ? scene : -1};
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bx[q] = min(bx[q], __shfl_xor(bx[q], o, 64));
+        bx[5] = max(bx[5], __shfl_xor(bx[5], o, 64));
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wbox[wave][q] = bx[q];
     }
     __syncthreads();
-    const int x0 = box[0], y0 = box[1], bw = -box[2] - x0 + 1, bh = -box[3] - y0 + 1;
-    const bool any = box[5] >= 0;
-    const bool tiled = any && box[4] == box[5] && (int64_t)bw * bh <= kSplatTile;  // uniform
+#pragma unroll
+    for (int w = 0; w < kSplatWaves; ++w) {
+        if (w == wave) continue;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bx[q] = min(bx[q], wbox[w][q]);
+        bx[5] = max(bx[5], wbox[w][5]);
+    }
+    const int x0 = bx[0], y0 = bx[1], bw = -bx[2] - x0 + 1, bh = -bx[3] - y0 + 1;
+    const bool any = bx[5] >= 0;
+    const bool tiled = any && bx[4] == bx[5] && (int64_t)bw * bh <= kSplatTile;  // uniform
     if (!tiled) {
-        // the particles along one ray all land on the same pixels: a plain
-        // read first, and an atomic only where it can still lower the value
-        // (a stale read costs one needless atomic; the minimum is the same)
+        // each particle's square straight into the image, eight pixels at a
+        // time (the particles along one ray all land on the same pixels, so
+        // most of them find the value already lower)
         if (ok) {
             const SceneDev &S = sc[scene];
-            for (int b = b0; b <= b1; ++b)
-                for (int a = a0; a <= a1; ++a) {
-                    uint32_t *px = &depth[S.depth_off + (uint32_t)b * (uint32_t)S.img_w + (uint32_t)a];
-                    if (bits < *px) atomicMin(px, bits);  // values only fall: a stale read is safe
+            int a = a0, b = b0;
+            while (b <= b1) {
+                uint32_t idx[8], val[8];
+                bool on[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    on[q] = b <= b1;
+                    idx[q] = on[q] ? S.depth_off + (uint32_t)b * (uint32_t)S.img_w + (uint32_t)a
+                                   : S.depth_off;  // in bounds even when unused
+                    val[q] = bits;
+                    if (++a > a1) {
+                        a = a0;
+                        ++b;
+                    }
                 }
+                lower_pixels(depth, idx, val, on);
+            }
         }
         return;
     }
-    const int m = bw * bh;
-    for (int e = threadIdx.x; e < m; e += blockDim.x) img[e] = 0x7f800000u;
-    __syncthreads();
     if (ok)
         for (int b = b0; b <= b1; ++b)
             for (int a = a0; a <= a1; ++a) atomicMin(&img[(b - y0) * bw + (a - x0)], bits);
     __syncthreads();
-    const SceneDev &T = sc[box[4]];
-    for (int e = threadIdx.x; e < m; e += blockDim.x) {
-        const uint32_t v = img[e];
-        if (v == 0x7f800000u) continue;
-        const int r = e / bw, c = e - r * bw;
-        uint32_t *px = &depth[T.depth_off + (uint32_t)(y0 + r) * (uint32_t)T.img_w + (uint32_t)(x0 + c)];
-        if (v < *px) atomicMin(px, v);
+    // the touched pixels of the tile into the image, four per thread at a time
+    const SceneDev &T = sc[bx[4]];
+    const int m = bw * bh;
+    for (int e0 = threadIdx.x; e0 < m; e0 += 4 * kSplatThreads) {
+        uint32_t idx[4], val[4];
+        bool on[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kSplatThreads;
+            val[q] = e < m ? img[e] : 0x7f800000u;
+            on[q] = val[q] != 0x7f800000u;
+            const int r = e / bw, c = e - r * bw;
+            idx[q] = on[q] ? T.depth_off + (uint32_t)(y0 + r) * (uint32_t)T.img_w + (uint32_t)(x0 + c)
+                           : T.depth_off;
+        }
+        lower_pixels(depth, idx, val, on);
     }
 }
 
