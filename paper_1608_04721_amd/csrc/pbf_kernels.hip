@@ -959,6 +959,18 @@ __global__ __launch_bounds__(1024) void k_tile_tables(
     __shared__ uint32_t hist[PBF_MAX_ITERS + 2];   // tiles per level, then running bucket offsets
     __shared__ uint32_t wc[1024 / 64][PBF_MAX_ITERS + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // every global load is issued first: the tile levels (tile r * 1024 +
+    // thread of each round) and the partial level sums, so the rounds below
+    // wait on LDS and barriers only
+    constexpr int kRounds = kFusedTiles / 1024;
+    int lv[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint32_t s = (uint32_t)r * 1024u + threadIdx.x;
+        lv[r] = s < T ? (int)tile_lvl[s] : 0;
+    }
+    uint32_t part = 0;
+    for (uint32_t e = threadIdx.x; e < n_part; e += blockDim.x) part += level_part[e];
     // exclusive scan of the tile counts, kScanItems consecutive tiles per thread
     uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x * kScanItems) {
@@ -983,10 +995,12 @@ __global__ __launch_bounds__(1024) void k_tile_tables(
     // bucket starts in descending level order
     for (int L = threadIdx.x; L <= K + 1; L += blockDim.x) hist[L] = 0;
     __syncthreads();
-    for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x) {
-        const uint32_t s = b0 + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if ((uint32_t)r * 1024u >= T) break;
+        const uint32_t s = (uint32_t)r * 1024u + threadIdx.x;
         const bool valid = s < T;
-        const int L = valid ? (int)tile_lvl[s] : 0;
+        const int L = lv[r];
         uint64_t rem = __ballot(valid);
         while (rem) {
             const int leader = __ffsll((unsigned long long)rem) - 1;
@@ -1010,12 +1024,14 @@ __global__ __launch_bounds__(1024) void k_tile_tables(
     __syncthreads();
     // stable scatter, 1024 tiles per round: rank inside the wave by ballots,
     // then across the waves of the round, then the bucket's running offset
-    for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if ((uint32_t)r * 1024u >= T) break;
         for (int i = threadIdx.x; i < nw * (PBF_MAX_ITERS + 1); i += blockDim.x) (&wc[0][0])[i] = 0;
         __syncthreads();
-        const uint32_t s = b0 + threadIdx.x;
+        const uint32_t s = (uint32_t)r * 1024u + threadIdx.x;
         const bool valid = s < T;
-        const int L = valid ? (int)tile_lvl[s] : 0;
+        const int L = lv[r];
         uint64_t rem = __ballot(valid);
         uint32_t rank = 0;
         while (rem) {
@@ -1042,8 +1058,6 @@ __global__ __launch_bounds__(1024) void k_tile_tables(
         __syncthreads();
     }
     // running count of particle-iterations (sum_i N_i) and of steps
-    uint32_t part = 0;
-    for (uint32_t e = threadIdx.x; e < n_part; e += blockDim.x) part += level_part[e];
     part = wave_sum(part);
     if (lane == 0) lds[wave] = part;
     __syncthreads();
