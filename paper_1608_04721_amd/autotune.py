@@ -28,7 +28,7 @@ CANDIDATES: Dict[str, tuple] = {
     "sort_scatter": (128, 256, 512, 1024),
     "sort_finish": (128, 256, 512, 1024),
     "tile_prepare": (64, 128, 256, 512),
-    "neighbours": (64, 128, 192, 256),
+    "neighbours": (128, 256, 384, 512),
     "lambda": (128, 256, 384, 512),
     "update": (128, 256, 384, 512),
     "commit": (128, 256, 512, 1024),

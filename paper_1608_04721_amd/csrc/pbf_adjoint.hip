@@ -87,7 +87,7 @@ __device__ __forceinline__ bool group_of(int64_t n, int64_t &p, uint32_t &sub)
 // forward kernels).  A thread takes one group of 8 codes of one particle;
 // a staged code is an LDS stage index, turned into its slot by a table of
 // the whole stage built first.
-__global__ __launch_bounds__(kNbrThreads) void k_adj_decode(
+__global__ __launch_bounds__(kDecodeThreads) void k_adj_decode(
     uint32_t tiles, const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
     const uint32_t *__restrict__ rows, int64_t n, uint32_t groups, const uint4 *__restrict__ nbr,
@@ -402,7 +402,7 @@ hipError_t enqueue_adjoint_step(const StepBuffers &b, const StepRecord &r, const
     // lanes per particle of the gather kernels: enough for about 2^19 threads
     const int lanes = n >= (int64_t(1) << 19) ? 1 : n >= (int64_t(1) << 18) ? 2 : n >= (int64_t(1) << 17) ? 4 : 8;
     const unsigned gl = blocks(n * lanes, tb);
-    hipLaunchKernelGGL(k_adj_decode, dim3(b.n_tiles * tile_split(b.n_tiles)), dim3(kNbrThreads), 0,
+    hipLaunchKernelGGL(k_adj_decode, dim3(b.n_tiles * tile_split(b.n_tiles)), dim3(kDecodeThreads), 0,
                        s, b.n_tiles, r.tile_order, r.tile_ge, r.tile_start, r.tile_count,
                        r.tile_rows, n, (uint32_t)(b.nbr_cap + 7) / 8, r.nbr, r.pmeta, w.nslot);
     ACHK(hipGetLastError());

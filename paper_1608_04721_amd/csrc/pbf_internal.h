@@ -17,7 +17,8 @@ constexpr int kStageRows = kStageEdge * kStageEdge;
 constexpr int kOwnRows = kTileEdge * kTileEdge;
 constexpr int kStageCap = 2304;    // float4 entries staged in LDS (36 KiB)
 constexpr int kTileThreads = 512;  // threads of a solver-pass tile workgroup (at most)
-constexpr int kNbrThreads = 256;   // threads of a neighbour-build tile workgroup (at most)
+constexpr int kNbrThreads = 512;   // threads of a neighbour-build tile workgroup (at most)
+constexpr int kDecodeThreads = 256;  // threads of a workgroup decoding a tile's codes (reverse pass)
 constexpr int kBndWords = kStageRows * (kStageEdge + 1);  // cell bounds of the staged rows
 constexpr int kRowWords = kBndWords + kStageRows + 1;     // saved tables per tile
 constexpr uint32_t kXcds = 8;       // accelerator complex dies of an MI355X (own L2 each)

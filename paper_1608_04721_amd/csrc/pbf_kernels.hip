@@ -1176,7 +1176,7 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
 }
 
 template <bool SPLIT>
-__global__ __launch_bounds__(kNbrThreads) void k_neighbours(
+__global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_neighbours(
     const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
     const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
     const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ cell_start,
