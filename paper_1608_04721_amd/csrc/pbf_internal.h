@@ -126,6 +126,7 @@ extern const int kDefaultBlock[K_COUNT];
 constexpr int kLevelBlock = 256;  // items per level-bucketing block (fixed: 4 waves)
 constexpr int kScanItems = 8;     // items per thread in the exclusive scans
 constexpr int kScanBlock = 256;   // threads of a scan block (2048 items)
+constexpr int kScanDirect = 1024;  // scans of up to this many blocks skip the top-level pass
 constexpr uint32_t kFusedTiles = 16384;  // up to this many tiles, one workgroup does the tile tables
 constexpr uint32_t kSplitTarget = 1024;  // tile workgroups that fill the chip (4 per CU)
 constexpr uint32_t kMaxSplit = 8;        // at most this many workgroups per tile (64 particles each)

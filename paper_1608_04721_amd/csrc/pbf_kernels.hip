@@ -531,11 +531,21 @@ __global__ void k_scan_top(uint32_t *__restrict__ part, uint32_t nb)
 }
 
 // clear: if not null (the same array as in), each count is zeroed once read,
-// which leaves the cell histogram ready for the next step
+// which leaves the cell histogram ready for the next step.  sum_parts: part
+// holds the per-block sums themselves (no k_scan_top), and each block adds
+// up those before it.
 __global__ void k_scan_apply(const uint32_t *in, uint32_t G, const uint32_t *__restrict__ part,
-                             uint32_t *__restrict__ out, uint32_t *clear)
+                             uint32_t *__restrict__ out, uint32_t *clear, bool sum_parts)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
+    uint32_t off = 0;
+    if (sum_parts) {  // uniform
+        uint32_t v = 0;
+        for (uint32_t i = threadIdx.x; i < blockIdx.x; i += blockDim.x) v += part[i];
+        block_exclusive_sum(v, lds, &off);
+    } else {
+        off = part[blockIdx.x];
+    }
     // each thread owns kScanItems consecutive cells
     const uint32_t base = blockIdx.x * (uint32_t)(blockDim.x * kScanItems) +
                           threadIdx.x * (uint32_t)kScanItems;
@@ -552,7 +562,7 @@ __global__ void k_scan_apply(const uint32_t *in, uint32_t G, const uint32_t *__r
         for (int q = 0; q < kScanItems; ++q)
             if (base + q < G) clear[base + q] = 0u;
     }
-    uint32_t run = part[blockIdx.x] + block_exclusive_sum(sum, lds, nullptr);
+    uint32_t run = off + block_exclusive_sum(sum, lds, nullptr);
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
         uint32_t e = base + q;
@@ -847,10 +857,18 @@ __global__ void k_tile_prepare(uint32_t n_tiles, const SceneDev *__restrict__ sc
         b = row_bound(t, cell_start, sy, sz, kTileEdge + 1);
     }
     const uint32_t count = wave_sum(b - a);
+    // four lanes per own row, each taking every fourth particle of it, with
+    // eight loads issued together (longer rows take another round)
+    static_assert(kOwnRows * 4 == 64, "four lanes per own row");
+    const int o = lane >> 2;
+    const uint32_t ao = __shfl(a, o, 64), bo = __shfl(b, o, 64);
     uint32_t mx = 0;
-    for (int o = 0; o < kOwnRows; ++o) {
-        const uint32_t ao = __shfl(a, o, 64), bo = __shfl(b, o, 64);
-        for (uint32_t e = ao + lane; e < bo; e += 64) mx = max(mx, (uint32_t)lvl[e]);
+    for (uint32_t e0 = ao + (uint32_t)(lane & 3); e0 < bo; e0 += 32) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = e0 + 4 * q < bo ? (uint32_t)lvl[e0 + 4 * q] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mx = max(mx, v[q]);
     }
     mx = wave_max(mx);
     if (lane == 0) {
@@ -1662,10 +1680,13 @@ static hipError_t enqueue_scan(uint32_t *in, uint32_t count, uint32_t *part, uin
                                bool clear_in, hipStream_t s, Timer *tm)
 {
     const unsigned nb = blocks_for(count, kScanBlock * kScanItems);
+    // up to kScanDirect blocks, each block of the apply pass adds up the
+    // block sums before it (a few loads per thread) instead of a third launch
+    const bool direct = nb <= (unsigned)kScanDirect;
     LAUNCH(K_SCAN_REDUCE, nb, kScanBlock, k_scan_reduce, in, count, part);
-    LAUNCH(K_SCAN_TOP, 1, 1024, k_scan_top, part, nb);
+    if (!direct) LAUNCH(K_SCAN_TOP, 1, 1024, k_scan_top, part, nb);
     LAUNCH(K_SCAN_APPLY, nb, kScanBlock, k_scan_apply, in, count, part, out,
-           clear_in ? in : nullptr);
+           clear_in ? in : nullptr, direct);
     return hipSuccess;
 }
 
