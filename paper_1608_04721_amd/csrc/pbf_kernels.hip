@@ -967,122 +967,110 @@ __global__ void k_level_scatter(uint32_t m, const uint8_t *__restrict__ lvl,
 // of the tiles by descending level with the prefix counts ge[L] (tiles with
 // level >= L), and the running totals -- what k_scan_* and k_level_* do in
 // six launches.  The order is the same: descending level, ties by tile index.
+// Each wave owns a contiguous chunk of tiles, held in registers: it scans
+// the counts and ranks the levels of its chunk by itself (lane L keeps the
+// running count of level L), so the waves meet at one barrier only.
+constexpr int kTableWaves = 16;                                  // 1024 threads
+constexpr int kTablePer = kFusedTiles / (kTableWaves * 64);      // tiles per lane, at most
 __global__ __launch_bounds__(1024) void k_tile_tables(
     uint32_t T, int K, const uint32_t *__restrict__ tile_count, const uint8_t *__restrict__ tile_lvl,
     uint32_t *__restrict__ tile_start, uint32_t *__restrict__ order, uint32_t *__restrict__ ge,
     const uint32_t *__restrict__ level_part, uint32_t n_part,
     unsigned long long *__restrict__ totals)
 {
-    __shared__ uint32_t lds[1024 / 64 + 1];
-    __shared__ uint32_t hist[PBF_MAX_ITERS + 2];   // tiles per level, then running bucket offsets
-    __shared__ uint32_t wc[1024 / 64][PBF_MAX_ITERS + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    // every global load is issued first: the tile levels (tile r * 1024 +
-    // thread of each round) and the partial level sums, so the rounds below
-    // wait on LDS and barriers only
-    constexpr int kRounds = kFusedTiles / 1024;
-    int lv[kRounds];
+    __shared__ uint32_t wlev[kTableWaves][PBF_MAX_ITERS + 1];  // per wave: tiles per level
+    __shared__ uint32_t wown[kTableWaves];                     // per wave: own particles
+    __shared__ uint32_t wpit[kTableWaves];                     // per wave: particle-iterations
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t J = (T + kTableWaves * 64 - 1) / (kTableWaves * 64);  // rounds of 64 per wave
+    const uint32_t t0 = (uint32_t)wave * J * 64u;                        // first tile of the chunk
+    // every global load first
+    uint32_t cnt[kTablePer];
+    int lv[kTablePer];  // -1: past the last tile
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const uint32_t s = (uint32_t)r * 1024u + threadIdx.x;
-        lv[r] = s < T ? (int)tile_lvl[s] : 0;
+    for (int r = 0; r < kTablePer; ++r) {
+        const uint32_t s = t0 + (uint32_t)r * 64u + (uint32_t)lane;
+        const bool ok = (uint32_t)r < J && s < T;
+        cnt[r] = ok ? tile_count[s] : 0u;
+        lv[r] = ok ? (int)tile_lvl[s] : -1;
     }
     uint32_t part = 0;
     for (uint32_t e = threadIdx.x; e < n_part; e += blockDim.x) part += level_part[e];
-    // exclusive scan of the tile counts, kScanItems consecutive tiles per thread
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < T; b0 += blockDim.x * kScanItems) {
-        const uint32_t base = b0 + threadIdx.x * (uint32_t)kScanItems;
-        uint32_t vals[kScanItems], sum = 0;
+    // the chunk's exclusive count scan and level ranks
+    uint32_t cex[kTablePer], rk[kTablePer];
+    uint32_t run = 0, lrun = 0;  // particles so far (uniform); tiles of level `lane` so far
 #pragma unroll
-        for (int q = 0; q < kScanItems; ++q) {
-            vals[q] = base + q < T ? tile_count[base + q] : 0u;
-            sum += vals[q];
+    for (int r = 0; r < kTablePer; ++r) {
+        if ((uint32_t)r >= J) break;
+        uint32_t inc = cnt[r];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
         }
-        uint32_t tot;
-        uint32_t run = carry + block_exclusive_sum(sum, lds, &tot);
-#pragma unroll
-        for (int q = 0; q < kScanItems; ++q) {
-            if (base + q < T) tile_start[base + q] = run;
-            run += vals[q];
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) tile_start[T] = carry;
-    // level histogram (one LDS atomic per level present in a wave), then
-    // bucket starts in descending level order
-    for (int L = threadIdx.x; L <= K + 1; L += blockDim.x) hist[L] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        if ((uint32_t)r * 1024u >= T) break;
-        const uint32_t s = (uint32_t)r * 1024u + threadIdx.x;
-        const bool valid = s < T;
+        cex[r] = run + inc - cnt[r];
+        run += __shfl(inc, 63, 64);
         const int L = lv[r];
-        uint64_t rem = __ballot(valid);
+        rk[r] = 0;
+        uint64_t rem = __ballot(L >= 0);
         while (rem) {
             const int leader = __ffsll((unsigned long long)rem) - 1;
             const int L0 = __shfl(L, leader, 64);
-            const uint64_t mm = __ballot(valid && L == L0);
-            if (lane == leader) atomicAdd(&hist[L0], (uint32_t)__popcll(mm));
+            const uint64_t mm = __ballot(L == L0);
+            const uint32_t base = __shfl(lrun, L0, 64);
+            if (L == L0) rk[r] = base + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull));
+            if (lane == L0) lrun += (uint32_t)__popcll(mm);
             rem &= ~mm;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int L = K; L >= 0; --L) {
-            const uint32_t c = hist[L];
-            hist[L] = run;  // first position of level L
-            run += c;
-            ge[L] = run;    // tiles with level >= L
-        }
-        ge[K + 1] = 0;
-    }
-    __syncthreads();
-    // stable scatter, 1024 tiles per round: rank inside the wave by ballots,
-    // then across the waves of the round, then the bucket's running offset
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        if ((uint32_t)r * 1024u >= T) break;
-        for (int i = threadIdx.x; i < nw * (PBF_MAX_ITERS + 1); i += blockDim.x) (&wc[0][0])[i] = 0;
-        __syncthreads();
-        const uint32_t s = (uint32_t)r * 1024u + threadIdx.x;
-        const bool valid = s < T;
-        const int L = lv[r];
-        uint64_t rem = __ballot(valid);
-        uint32_t rank = 0;
-        while (rem) {
-            const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int L0 = __shfl(L, leader, 64);
-            const uint64_t mm = __ballot(valid && L == L0);
-            if (valid && L == L0) rank = (uint32_t)__popcll(mm & ((1ull << lane) - 1ull));
-            if (lane == leader) wc[wave][L0] = (uint32_t)__popcll(mm);
-            rem &= ~mm;
-        }
-        __syncthreads();
-        if (valid) {
-            uint32_t before = 0;
-            for (int w = 0; w < wave; ++w) before += wc[w][L];
-            order[hist[L] + before + rank] = s;
-        }
-        __syncthreads();
-        // advance the running offsets by this round's counts
-        for (int L2 = threadIdx.x; L2 <= K; L2 += blockDim.x) {
-            uint32_t c = 0;
-            for (int w = 0; w < nw; ++w) c += wc[w][L2];
-            hist[L2] += c;
-        }
-        __syncthreads();
-    }
-    // running count of particle-iterations (sum_i N_i) and of steps
     part = wave_sum(part);
-    if (lane == 0) lds[wave] = part;
+    if (lane <= K) wlev[wave][lane] = lrun;
+    if (lane == 0) {
+        wown[wave] = run;
+        wpit[wave] = part;
+    }
     __syncthreads();
+    // level `lane`: tiles in all waves and in the waves before this one;
+    // particles before this wave's chunk
+    uint32_t tot = 0, pre = 0, own_pre = 0, own_tot = 0;
+#pragma unroll
+    for (int w = 0; w < kTableWaves; ++w) {
+        const uint32_t c = lane <= K ? wlev[w][lane] : 0u;
+        const uint32_t o = wown[w];
+        tot += c;
+        own_tot += o;
+        if (w < wave) {
+            pre += c;
+            own_pre += o;
+        }
+    }
+    // tiles of higher levels: a suffix sum over the lanes
+    uint32_t suf = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_down(suf, o, 64);
+        if (lane + o < 64) suf += u;
+    }
+    const uint32_t above = suf - tot;  // first position of level `lane`
+    if (wave == 0 && lane <= K + 1) ge[lane] = lane <= K ? suf : 0u;
+    const uint32_t first = above + pre;  // this wave's first position of level `lane`
+#pragma unroll
+    for (int r = 0; r < kTablePer; ++r) {
+        if ((uint32_t)r >= J) break;
+        const int L = lv[r];
+        const uint32_t f = __shfl(first, L >= 0 ? L : 0, 64);
+        if (L >= 0) {
+            const uint32_t s = t0 + (uint32_t)r * 64u + (uint32_t)lane;
+            order[f + rk[r]] = s;
+            tile_start[s] = own_pre + cex[r];
+        }
+    }
     if (threadIdx.x == 0) {
+        tile_start[T] = own_tot;
         unsigned long long pit = 0;
-        for (int w = 0; w < nw; ++w) pit += lds[w];
-        totals[0] += pit;
+#pragma unroll
+        for (int w = 0; w < kTableWaves; ++w) pit += wpit[w];
+        totals[0] += pit;  // running count of particle-iterations (sum_i N_i)
         totals[1] += 1ull;
     }
 }
