@@ -259,7 +259,9 @@ pbf_status pbf_get_counts(const pbf_ctx *ctx, int32_t *n_scenes, int64_t *n_tota
 pbf_status pbf_set_graph(pbf_ctx *ctx, int32_t enable);
 
 /* Launch shape of one kernel class (threads per block, a multiple of 64 in
- * [64, 1024]); 0 restores the default.  Kernel classes are numbered
+ * [64, 1024], at most 512 for the neighbour, lambda and update tile kernels;
+ * some classes have a fixed shape and accept only their default); 0 restores
+ * the default.  Kernel classes are numbered
  * 0..pbf_kernel_count()-1 and named by pbf_kernel_name(). */
 int32_t pbf_kernel_count(void);
 const char *pbf_kernel_name(int32_t kernel);  /* NULL if out of range */

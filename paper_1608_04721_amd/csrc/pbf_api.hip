@@ -834,7 +834,7 @@ pbf_status pbf_set_block_size(pbf_ctx *c, int32_t kernel, int32_t threads)
     if (threads == 0) threads = kDefaultBlock[kernel];
     if (threads < 64 || threads > max_block(kernel) || threads % 64)
         return fail(c, PBF_ERR_INVALID_ARG, "threads must be a multiple of 64 in [64, 1024] "
-                                            "(at most 256 for neighbours, 512 for lambda/update)");
+                                            "(at most 512 for neighbours, lambda and update)");
     if (fixed_shape(kernel) && threads != kDefaultBlock[kernel])
         return fail(c, PBF_ERR_INVALID_ARG, "this kernel has a fixed launch shape");
     if (c->ls.block[kernel] != threads) {
