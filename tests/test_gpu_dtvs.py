@@ -67,6 +67,33 @@ def test_full_size_tank_levels():
     print("tank levels", np.bincount(lv_ref, minlength=11)[5:])
 
 
+def test_wide_splats_and_moving_tank():
+    # splats of up to 16 pixels: every workgroup's box exceeds the LDS tile
+    # and each particle writes its square to the image directly
+    blk = scenes.block(14, 10, 12, seed=9, n_min=2, n_max=7, vel_sigma=0.3)
+    lo = blk.x0.min(axis=0).astype(np.float64)
+    hi = blk.x0.max(axis=0).astype(np.float64)
+    mid = (lo + hi) / 2
+    sc = scenes.with_dtvs(blk, camera=(mid[0] + 0.1, mid[1] + 0.3, lo[2] - 0.8), target=mid,
+                          focal=500.0, d_far=0.4)
+    with _sim(sc) as sim:
+        for _ in range(3):
+            x = sim.positions().astype(np.float64)
+            sim.step(1)
+            assert np.array_equal(sim.debug_levels().astype(np.int32), oracle.levels(sc, x))
+    # the full tank after some motion: workgroups straddling the end of a
+    # cell row take the direct path, the others the LDS tile
+    tank = scenes.tank_1m()
+    sc = scenes.with_dtvs(tank, camera=tank.camera, target=(3.2, 1.6, 3.2), d_far=4.0)
+    with _sim(sc) as sim:
+        sim.set_graph(True)
+        sim.step(8)
+        x = sim.positions().astype(np.float64)
+        sim.step(1)
+        lv = sim.debug_levels().astype(np.int32)
+    assert np.array_equal(lv, oracle.levels(sc, x))
+
+
 def test_batch_mixes_level_sources():
     a = _side_view(scenes.block(9, 7, 8, seed=6, n_min=1, n_max=6, vel_sigma=0.2))
     b = scenes.dam_break_4k().with_lod(scenes.LOD_DTC, n_min=2, n_max=5)
