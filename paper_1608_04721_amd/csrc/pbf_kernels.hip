@@ -826,15 +826,39 @@ __device__ bool tile_tables(const TileLoc &t, const uint32_t *__restrict__ cell_
 }
 
 // copy the staged rows of `src` into LDS, plus the far-away entry at
-// kFarCode that pads neighbour groups (all threads; ends with a barrier)
+// kFarCode that pads neighbour groups (all threads; ends with a barrier).
+// Wave w copies rows w, w + nw, ...: the first 64 entries of kStageBatch
+// of its rows are loaded together, so the wave waits once for all of them;
+// rows longer than 64 entries finish row by row.
+constexpr int kStageBatch = 5;
 __device__ __forceinline__ void tile_stage(const TileTables &tb, const float4 *__restrict__ src,
                                            float4 *__restrict__ stage)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (threadIdx.x == 0) stage[kFarCode] = make_float4(kFar, kFar, kFar, 0.f);
-    for (int r = wave; r < kStageRows; r += nw) {
-        const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0, b0 = tb.base[r];
-        for (uint32_t e = lane; e < len; e += 64) stage[b0 + e] = src[g0 + e];
+    for (int r0 = wave; r0 < kStageRows; r0 += kStageBatch * nw) {
+        float4 v[kStageBatch];
+        uint32_t dst[kStageBatch];
+        bool on[kStageBatch];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) {
+            const int r = min(r0 + j * nw, kStageRows - 1);
+            const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0;
+            on[j] = r0 + j * nw < kStageRows && (uint32_t)lane < len;
+            dst[j] = tb.base[r] + (uint32_t)lane;
+            v[j] = on[j] ? src[g0 + (uint32_t)lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j)
+            if (on[j]) stage[dst[j]] = v[j];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) {
+            const int r = r0 + j * nw;
+            if (r < kStageRows) {
+                const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0, b0 = tb.base[r];
+                for (uint32_t e = (uint32_t)lane + 64u; e < len; e += 64) stage[b0 + e] = src[g0 + e];
+            }
+        }
     }
     __syncthreads();
 }
