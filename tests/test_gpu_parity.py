@@ -258,15 +258,17 @@ def test_capacity_not_a_multiple_of_eight(extra):
             assert np.array_equal(b.positions(), x) and np.array_equal(b.velocities(), v)
 
 
-@pytest.mark.parametrize("side", [9.8, 12.0])
+@pytest.mark.parametrize("side", [9.8, 12.0, 13.5])
 def test_many_tiles(side):
     # a small block in a large box: 15,625 tiles (the one-workgroup tile
-    # tables with sixteen tiles per lane) or 27,000 (more than that kernel
-    # books: the multi-launch tile scan and level bucketing)
+    # tables with sixteen tiles per lane), 27,000 (more than that kernel
+    # books: the multi-launch tile scan and level bucketing), or 2.46M cells
+    # (a cell scan of more than 1,024 blocks, with its top-level pass)
     sc = scenes.block(10, 8, 9, seed=15, n_min=1, n_max=5, levels="random", vel_sigma=0.3,
                       box=(np.zeros(3), np.full(3, side)), origin=(side / 2 - 1.0, 0.0, side / 2 - 1.0))
     tiles = np.prod([-(-int(d) // 4) for d in sc.dims])
     assert (tiles > 16384) == (side > 10.0) and tiles > 15 * 1024
+    assert (np.prod(sc.dims.astype(np.int64)) > 1024 * 2048) == (side > 13.0)
     x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
     with _sim(sc) as sim:
         sim.step(1)
