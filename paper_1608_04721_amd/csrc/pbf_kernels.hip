@@ -17,7 +17,8 @@
 //               group g of particle p at [g * n + p]; a code is the
 //               neighbour's index in the tile's LDS stage, or row << 10 |
 //               offset when the stage does not fit in LDS
-//   pmeta/pslot u32[n]     level << 16 | neighbour count, and slot, per p
+//   pmeta/pslot u32[n]     neighbour count, level and own index in the LDS
+//                          stage (13, 6 and 13 bits), and slot, per p
 //
 // A tile's workgroup stages the 6^3 cells around its 4^3 cells (36 x-rows of
 // 6 cells, contiguous slot ranges) into LDS once per pass and evaluates all
@@ -1115,8 +1116,8 @@ __global__ __launch_bounds__(1024) void k_tile_tables(
 //
 // Each window is scanned in chunks of 32 candidates, four candidates per
 // round (their loads issued together) into a 32-bit hit mask; the hits then
-// become codes in candidate order.  Codes collect four at a time in a 64-bit
-// word; every eighth code stores one 16-byte group.
+// become codes in candidate order, each stored as a 16-bit value into its
+// slot of the particle's current 16-byte group.
 template <bool FITS>
 __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const float4 *__restrict__ stage,
                                                     const float4 *__restrict__ xs, float h2, uint32_t p0,
