@@ -186,7 +186,7 @@ struct StepBuffers {
     uint32_t *tile_rows;     // [n_tiles][kRowWords] stage layout of each tile
     // per particle, p order
     uint4 *nbr;              // [nbr_stride / 8][n] groups of eight u16 neighbour codes
-    uint32_t *pmeta;         // level << 16 | neighbour count
+    uint32_t *pmeta;         // neighbour count, level, own stage index (see make_meta)
     uint32_t *pslot;         // slot of particle p
     uint32_t *err;
     uint32_t *level_part;    // per lod_predict block: sum of N_i
