@@ -3,8 +3,10 @@
 Bit-exact: cell keys, sort permutation, neighbour sets and levels (with the
 guard bands of tests/parity.py).  Floating point: positions within 1e-5 of
 the largest box extent after one step, lambdas within the FP32 bound
-derived in tests/parity.py / the design notes.
+derived in tests/parity.py.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch  # noqa: F401  (first import can be slow; keep it out of test timeouts)
@@ -273,6 +275,35 @@ def test_many_tiles(side):
     with _sim(sc) as sim:
         sim.step(1)
         _check_step(sc, sim, x_ref, v_ref, info)
+
+
+SHAPES = [
+    {"neighbours": 384, "lambda": 256, "update": 384, "lod_predict": 128, "sort_finish": 1024,
+     "tile_prepare": 64, "commit": 512},
+    {"neighbours": 128, "lambda": 128, "update": 128, "sort_scatter": 1024, "contacts": 1024},
+]
+
+
+@pytest.mark.parametrize("name", ["block", "dam_break_262k"])
+def test_launch_shapes_do_not_change_results(name):
+    # every sum runs in a fixed order per particle, so other block sizes
+    # (split tiles for the small block, one workgroup per tile for the 262k
+    # dam break) give the same bits
+    if name == "block":
+        sc = dataclasses.replace(
+            scenes.block(30, 20, 24, seed=3, n_min=2, n_max=6, levels="random", vel_sigma=0.3),
+            obstacles=((scenes.OB_SPHERE, (0.75, 0.3, 0.6), (0.2, 0.0, 0.0)),), stab_iters=1, stab_s=3)
+    else:
+        sc = scenes.dam_break_262k()
+    with _sim(sc) as ref:
+        ref.step(3)
+        x_ref = ref.positions()
+    for shape in SHAPES:
+        with _sim(sc) as sim:
+            for k, t in shape.items():
+                sim.set_block_size(k, t)
+            sim.step(3)
+            assert np.array_equal(sim.positions(), x_ref), shape
 
 
 def test_resume_from_saved_state_bit_identical():
