@@ -199,6 +199,10 @@ typedef struct pbf_step_stats {
     int64_t total_particle_iterations;   /* sum over every step since create or
                                             pbf_set_state, counted on the device */
     int64_t total_steps;                 /* steps counted in the same span */
+    int32_t max_stage;                   /* largest neighbourhood staged by one tile
+                                            (particles in its 6^3 cells) */
+    int32_t tiles_unstaged;              /* tiles whose neighbourhood exceeded the
+                                            on-chip stage and was read from HBM */
 } pbf_step_stats;
 
 /* ---------------- core entry points ---------------- */
@@ -251,6 +255,21 @@ pbf_status pbf_batch_set_obstacles(pbf_ctx *ctx, int32_t scene, const pbf_contac
 pbf_status pbf_batch_read_positions(pbf_ctx *ctx, int32_t scene, float *out,
                                     int32_t out_on_device);
 pbf_status pbf_get_counts(const pbf_ctx *ctx, int32_t *n_scenes, int64_t *n_total);
+
+/* ---------------- device memory ---------------- */
+
+/* Bound on the device memory the library holds, for callers that share the
+ * GPU and must cap it: once set, any device allocation the library would
+ * make beyond `bytes` in total (all contexts of the process) fails, and the
+ * entry point that needed it returns PBF_ERR_OUT_OF_MEMORY with the
+ * context unchanged (pbf_create and pbf_batch_create return no context).
+ * 0 removes the bound (the default); memory already held is unaffected.
+ * PBF_ERR_INVALID_ARG if bytes < 0.  Process-wide; safe to call from any
+ * thread. */
+pbf_status pbf_set_memory_limit(int64_t bytes);
+
+/* Device bytes held by the library now, all contexts of the process. */
+int64_t pbf_device_bytes(void);
 
 /* ---------------- execution control ---------------- */
 

@@ -258,7 +258,8 @@ class Sim:
                 "particle_iterations": s.particle_iterations,
                 "neighbour_pairs": s.neighbour_pairs, "max_neighbours": s.max_neighbours,
                 "total_particle_iterations": s.total_particle_iterations,
-                "total_steps": s.total_steps}
+                "total_steps": s.total_steps, "max_stage": s.max_stage,
+                "tiles_unstaged": s.tiles_unstaged}
 
     def debug_keys(self) -> np.ndarray:
         out = np.empty(self.n, np.uint32)

@@ -69,7 +69,7 @@ class PbfStepStats(ctypes.Structure):
     _fields_ = [("n_iters", c_i32), ("active", c_i64 * PBF_MAX_ITERS),
                 ("particle_iterations", c_i64), ("neighbour_pairs", c_i64),
                 ("max_neighbours", c_i32), ("total_particle_iterations", c_i64),
-                ("total_steps", c_i64)]
+                ("total_steps", c_i64), ("max_stage", c_i32), ("tiles_unstaged", c_i32)]
 
 
 P = ctypes.POINTER
@@ -91,6 +91,8 @@ SIGNATURES = {
     "pbf_batch_set_obstacles": (c_i32, [CTX, c_i32, P(PbfContactDesc)]),
     "pbf_batch_read_positions": (c_i32, [CTX, c_i32, c_vp, c_i32]),
     "pbf_get_counts": (c_i32, [CTX, P(c_i32), P(c_i64)]),
+    "pbf_set_memory_limit": (c_i32, [c_i64]),
+    "pbf_device_bytes": (c_i64, []),
     "pbf_set_graph": (c_i32, [CTX, c_i32]),
     "pbf_kernel_count": (c_i32, []),
     "pbf_kernel_name": (ctypes.c_char_p, [c_i32]),

@@ -5,8 +5,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/pbf.h"
@@ -67,6 +70,46 @@ static hipError_t timer_collect(Timer *tm, hipStream_t s)
     return hipSuccess;
 }
 
+// Device memory of the library.  Every allocation and free goes through
+// dev_malloc / dev_free, which keep the bytes held by all contexts of the
+// process and enforce the limit set with pbf_set_memory_limit.
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void *, size_t> g_mem_size;
+int64_t g_mem_held = 0;
+int64_t g_mem_limit = 0;  // 0: none
+}  // namespace
+
+hipError_t dev_malloc(void **p, size_t bytes)
+{
+    bytes = std::max<size_t>(bytes, 1);
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    *p = nullptr;
+    if (g_mem_limit > 0 && g_mem_held + (int64_t)bytes > g_mem_limit) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    g_mem_size[*p] = bytes;
+    g_mem_held += (int64_t)bytes;
+    return hipSuccess;
+}
+
+void dev_free(void *p)
+{
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        auto it = g_mem_size.find(p);
+        if (it != g_mem_size.end()) {
+            g_mem_held -= (int64_t)it->second;
+            g_mem_size.erase(it);
+        }
+    }
+    (void)hipFree(p);
+}
+
 }  // namespace pbf
 
 using namespace pbf;
@@ -98,6 +141,8 @@ struct pbf_ctx {
     bool roll_valid = false;
     size_t depth_cap = 0;  // pixels allocated in b.depth (DTVS depth images)
     uint32_t range_cap = 0;  // words allocated in b.range (automatic distance ranges)
+    // b.depth and b.range are owned here (not in allocs): they are replaced
+    // when a larger layout is needed
     // average-density buffers (allocated by the first pbf_density)
     pbf::DensityBuffers dens{};
     float *dens_rho_id = nullptr;
@@ -219,7 +264,7 @@ template <class T>
 hipError_t dalloc(pbf_ctx *c, T **p, size_t count)
 {
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    hipError_t e = dev_malloc(&q, std::max<size_t>(count, 1) * sizeof(T));
     if (e == hipSuccess) {
         c->allocs.push_back(q);
         *p = (T *)q;
@@ -367,6 +412,20 @@ const char *pbf_last_error(const pbf_ctx *ctx)
     return ctx ? ctx->err.c_str() : "null context";
 }
 
+pbf_status pbf_set_memory_limit(int64_t bytes)
+{
+    if (bytes < 0) return PBF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_limit = bytes;
+    return PBF_OK;
+}
+
+int64_t pbf_device_bytes(void)
+{
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    return g_mem_held;
+}
+
 int32_t pbf_kernel_count(void) { return K_COUNT; }
 
 const char *pbf_kernel_name(int32_t k)
@@ -383,10 +442,11 @@ void pbf_destroy(pbf_ctx *c)
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }
-    for (void *p : c->allocs) (void)hipFree(p);
-    for (float *p : c->ckpt) (void)hipFree(p);
-    for (void *p : c->rs.bufs) (void)hipFree(p);
-    if (c->b.depth) (void)hipFree(c->b.depth);
+    for (void *p : c->allocs) dev_free(p);
+    for (float *p : c->ckpt) dev_free(p);
+    for (void *p : c->rs.bufs) dev_free(p);
+    dev_free(c->b.depth);
+    dev_free(c->b.range);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -617,47 +677,58 @@ pbf_status pbf_batch_set_lod(pbf_ctx *c, int32_t scene, const pbf_lod_desc *lod)
         return fail(c, PBF_ERR_INVALID_ARG, "unknown LOD mode");
     }
     s.lod_mode = lod->mode;
-    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
-    c->scenes[scene] = s;
-    c->roll_valid = false;  // a recorded rollout no longer replays the same steps
-    // lay the depth images of all DTVS scenes out one after another
+    // The new scene table with the layout of the depth images of all DTVS
+    // scenes (one after another) and of the automatic-range words.  Nothing
+    // of the context changes until every check and allocation has passed.
+    std::vector<SceneDev> ns = c->scenes;
+    ns[scene] = s;
     size_t pixels = 0;
-    for (auto &sd : c->scenes) {
+    for (auto &sd : ns) {
         sd.depth_off = (uint32_t)pixels;
         if (sd.lod_mode == PBF_LOD_DTVS) pixels += (size_t)sd.img_w * (size_t)sd.img_h;
+        if (pixels > 0xffffffffull) return fail(c, PBF_ERR_INVALID_ARG, "DTVS images too large in total");
     }
-    if (pixels > 0xffffffffull) return fail(c, PBF_ERR_INVALID_ARG, "DTVS images too large in total");
-    if (pixels != c->b.n_depth) drop_graphs(c);  // the step's launches change
-    if (pixels > c->depth_cap) {
-        drop_graphs(c);
-        if (c->b.depth) (void)hipFree(c->b.depth);
-        c->b.depth = nullptr;
-        c->depth_cap = 0;
-        c->b.n_depth = 0;
-        hipError_t e = hipMalloc((void **)&c->b.depth, pixels * sizeof(uint32_t));
-        if (e != hipSuccess) {
-            c->b.depth = nullptr;
-            return hip_fail(c, e, "depth images");
-        }
-        c->depth_cap = pixels;
-    }
-    c->b.n_depth = (uint32_t)pixels;
-    // and the automatic-range words of every such scene's cameras
     uint32_t words = 0;
-    for (auto &sd : c->scenes) {
+    for (auto &sd : ns) {
         sd.range_off = words;
         if (sd.auto_range && (sd.lod_mode == PBF_LOD_DTC || sd.lod_mode == PBF_LOD_DTVS))
             words += 2u * (uint32_t)sd.n_cam;
     }
-    if (words != c->b.n_range) drop_graphs(c);
+    uint32_t *new_depth = nullptr, *new_range = nullptr;
+    if (pixels > c->depth_cap) {
+        hipError_t e = dev_malloc((void **)&new_depth, pixels * sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail(c, e, "depth images");
+    }
     if (words > c->range_cap) {
-        uint32_t *r = nullptr;
-        hipError_t e = dalloc(c, &r, (size_t)words);
-        if (e != hipSuccess) return hip_fail(c, e, "range words");
-        c->b.range = r;  // the old words stay with the context's allocations
+        hipError_t e = dev_malloc((void **)&new_range, (size_t)words * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            dev_free(new_depth);
+            return hip_fail(c, e, "range words");
+        }
+    }
+    // commit: the stream is idle before buffers that captured steps use change
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        dev_free(new_depth);
+        dev_free(new_range);
+        return hip_fail(c, e, "stream synchronize");
+    }
+    if (new_depth || new_range || pixels != c->b.n_depth || words != c->b.n_range)
+        drop_graphs(c);  // the step's launches or their buffers change
+    if (new_depth) {
+        dev_free(c->b.depth);
+        c->b.depth = new_depth;
+        c->depth_cap = pixels;
+    }
+    if (new_range) {
+        dev_free(c->b.range);
+        c->b.range = new_range;
         c->range_cap = words;
     }
+    c->b.n_depth = (uint32_t)pixels;
     c->b.n_range = words;
+    c->scenes = ns;
+    c->roll_valid = false;  // a recorded rollout no longer replays the same steps
     if (!lv.empty())
         HIPCHK(c, hipMemcpyAsync(c->b.lev_by_id + c->pid_off[scene], lv.data(), lv.size(),
                                  hipMemcpyHostToDevice, c->stream), "upload levels");
@@ -895,6 +966,17 @@ pbf_status pbf_stats(pbf_ctx *c, pbf_step_stats *o)
         o->neighbour_pairs += cnt;
         o->max_neighbours = std::max(o->max_neighbours, cnt);
     }
+    // staged neighbourhood of every tile with particles (saved stage tables)
+    std::vector<uint32_t> tcount, rows;
+    const size_t T = c->b.n_tiles;
+    if ((st = d2h(c, tcount, c->b.tile_count, T)) != PBF_OK) return st;
+    if ((st = d2h(c, rows, c->b.tile_rows, T * (size_t)kRowWords)) != PBF_OK) return st;
+    for (size_t t = 0; t < T; ++t) {
+        if (!tcount[t]) continue;
+        const uint32_t staged = rows[t * (size_t)kRowWords + kBndWords + kStageRows];
+        o->max_stage = std::max(o->max_stage, (int32_t)staged);
+        if (staged > (uint32_t)kStageCap) o->tiles_unstaged += 1;
+    }
     return latched(c);
 }
 
@@ -1007,30 +1089,47 @@ pbf_status pbf_density(pbf_ctx *c, double *out, float *rho_rel, int32_t on_devic
     }
     DensityBuffers &d = c->dens;
     if (!d.out) {
+        // allocated by the first call and kept; a failed attempt frees what
+        // it allocated and leaves the context as it was
         const size_t T = c->b.n_tiles, parts = (T + kXcds - 1) / kXcds * kXcds;
+        DensityBuffers nd{};
+        float *rho_id_buf = nullptr;
+        std::vector<void *> got;
         hipError_t e = hipSuccess;
-        if (e == hipSuccess) e = dalloc(c, &d.xs, (size_t)n);
-        if (e == hipSuccess) e = dalloc(c, &d.key, (size_t)n);
-        if (e == hipSuccess) e = dalloc(c, &d.nbr, (size_t)n * (size_t)(c->b.nbr_stride / 8));
-        if (e == hipSuccess) e = dalloc(c, &d.pmeta, (size_t)n);
-        if (e == hipSuccess) e = dalloc(c, &d.pslot, (size_t)n);
-        if (e == hipSuccess) e = dalloc(c, &d.tile_rows, T * kRowWords);
-        if (e == hipSuccess) e = dalloc(c, &d.tile_order, T);
-        if (e == hipSuccess) e = dalloc(c, &d.tile_start, T + 1);
-        if (e == hipSuccess) e = dalloc(c, &d.tile_count, T);
-        if (e == hipSuccess) e = dalloc(c, &d.tile_ge, (size_t)PBF_MAX_ITERS + 2);
-        if (e == hipSuccess) e = dalloc(c, &d.tile_lvl, T);
-        if (e == hipSuccess) e = dalloc(c, &d.err, 1);
-        if (e == hipSuccess) e = dalloc(c, &d.totals, 2);
-        if (e == hipSuccess) e = dalloc(c, &d.rho_slot, (size_t)n);
-        if (e == hipSuccess) e = dalloc(c, &d.part_sum, parts);
-        if (e == hipSuccess) e = dalloc(c, &d.part_max, parts);
-        if (e == hipSuccess) e = dalloc(c, &c->dens_rho_id, (size_t)n);
-        if (e == hipSuccess) e = dalloc(c, &d.out, 2);
+        auto al = [&](auto **ptr, size_t count) {
+            if (e != hipSuccess) return;
+            void *q = nullptr;
+            e = dev_malloc(&q, std::max<size_t>(count, 1) * sizeof(**ptr));
+            if (e == hipSuccess) {
+                got.push_back(q);
+                *ptr = (std::remove_reference_t<decltype(*ptr)>)q;
+            }
+        };
+        al(&nd.xs, (size_t)n);
+        al(&nd.key, (size_t)n);
+        al(&nd.nbr, (size_t)n * (size_t)(c->b.nbr_stride / 8));
+        al(&nd.pmeta, (size_t)n);
+        al(&nd.pslot, (size_t)n);
+        al(&nd.tile_rows, T * kRowWords);
+        al(&nd.tile_order, T);
+        al(&nd.tile_start, T + 1);
+        al(&nd.tile_count, T);
+        al(&nd.tile_ge, (size_t)PBF_MAX_ITERS + 2);
+        al(&nd.tile_lvl, T);
+        al(&nd.err, 1);
+        al(&nd.totals, 2);
+        al(&nd.rho_slot, (size_t)n);
+        al(&nd.part_sum, parts);
+        al(&nd.part_max, parts);
+        al(&rho_id_buf, (size_t)n);
+        al(&nd.out, 2);
         if (e != hipSuccess) {
-            d.out = nullptr;  // allocated parts are freed by pbf_destroy; retried next call
+            for (void *q : got) dev_free(q);
             return hip_fail(c, e, "density buffers");
         }
+        c->allocs.insert(c->allocs.end(), got.begin(), got.end());
+        d = nd;
+        c->dens_rho_id = rho_id_buf;
     }
     float *rho_id = rho_rel ? (on_device ? rho_rel : c->dens_rho_id) : nullptr;
     HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), c->stream), "clear faults");
@@ -1128,12 +1227,16 @@ pbf_status pbf_rollout_forward(pbf_ctx *c, int32_t n_steps, int32_t ckpt_every)
     const size_t n3 = (size_t)c->n_total * 3;
     const int32_t nck = (n_steps + ckpt_every - 1) / ckpt_every;
     if (c->ckpt.size() != (size_t)(2 * nck)) {  // kept from the last rollout if the count matches
-        for (float *p : c->ckpt) (void)hipFree(p);
+        for (float *p : c->ckpt) dev_free(p);
         c->ckpt.clear();
         for (int32_t k = 0; k < 2 * nck; ++k) {
             float *p = nullptr;
-            hipError_t e = hipMalloc((void **)&p, std::max<size_t>(n3, 1) * sizeof(float));
-            if (e != hipSuccess) return hip_fail(c, e, "checkpoint buffers");
+            hipError_t e = dev_malloc((void **)&p, std::max<size_t>(n3, 1) * sizeof(float));
+            if (e != hipSuccess) {
+                for (float *q : c->ckpt) dev_free(q);
+                c->ckpt.clear();
+                return hip_fail(c, e, "checkpoint buffers");
+            }
             c->ckpt.push_back(p);
         }
     }
@@ -1172,12 +1275,12 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
     const int32_t seg_len = std::min(C, T);
     auto &rs = c->rs;
     if (rs.seg_len != seg_len) {  // (re)allocate the work buffers for this segment length
-        for (void *p : rs.bufs) (void)hipFree(p);
+        for (void *p : rs.bufs) dev_free(p);
         rs.bufs.clear();
         rs.seg_len = 0;
         auto alloc = [&](size_t bytes) -> void * {
             void *p = nullptr;
-            if (hipMalloc(&p, std::max<size_t>(bytes, 1)) != hipSuccess) return nullptr;
+            if (dev_malloc(&p, bytes) != hipSuccess) return nullptr;
             rs.bufs.push_back(p);
             return p;
         };
@@ -1217,7 +1320,7 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
             for (int k = 0; k <= K && ok; ++k) ok = (r.snap[k] = (float4 *)alloc((size_t)n * 16)) != nullptr;
         }
         if (!ok) {
-            for (void *p : rs.bufs) (void)hipFree(p);
+            for (void *p : rs.bufs) dev_free(p);
             rs.bufs.clear();
             return fail(c, PBF_ERR_OUT_OF_MEMORY, "rollout backward buffers");
         }

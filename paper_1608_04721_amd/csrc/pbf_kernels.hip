@@ -1515,7 +1515,8 @@ __global__ void k_density_keys(int64_t n, const SceneDev *__restrict__ sc,
 }
 
 // rho_i / rho0 (Eqs. 5-6, the particle itself included) of every particle at
-// the positions after the last step, over that step's neighbour sets; the
+// the positions after the last step, over neighbour sets found afresh at
+// those positions (enqueue_density sorts and searches them anew); the
 // quality measure of the paper's evaluation is the average over all
 // particles.  Per workgroup: the sum (double, reduced in a fixed order) and
 // the maximum; k_density_finish adds the workgroups up, again in a fixed

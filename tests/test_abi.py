@@ -109,3 +109,36 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+@pytest.mark.parametrize("where,bad", [("x0", np.nan), ("x0", np.inf), ("v0", -np.inf),
+                                       ("v0", np.nan)])
+def test_nonfinite_inputs_rejected_on_host(lib, where, bad):
+    """pbf_create checks host inputs for NaN/Inf before any HIP call and
+    returns PBF_ERR_NONFINITE without a context."""
+    from paper_1608_04721_amd import _lib
+    p = _params()
+    x = np.full(3 * p.n, 0.5, np.float32)
+    v = np.zeros(3 * p.n, np.float32)
+    (x if where == "x0" else v)[7] = bad
+    ctx = ctypes.c_void_p()
+    st = lib.pbf_create(ctypes.byref(p), x.ctypes.data, v.ctypes.data, 0, None, ctypes.byref(ctx))
+    assert st == _lib.PBF_ERR_NONFINITE
+    assert not ctx.value
+    # a batch with the bad value in its second scene is rejected the same way
+    pp = (_lib.PbfParams * 2)(_params(), _params())
+    x2 = np.concatenate([np.full(3 * p.n, 0.5, np.float32), x])
+    v2 = np.concatenate([np.zeros(3 * p.n, np.float32), v])
+    st = lib.pbf_batch_create(2, pp, x2.ctypes.data, v2.ctypes.data, 0, None, ctypes.byref(ctx))
+    assert st == _lib.PBF_ERR_NONFINITE
+    assert not ctx.value
+
+
+def test_memory_limit_arguments(lib):
+    """The device-memory bound is host state: a negative bound is rejected,
+    and with no context alive the library holds no device memory."""
+    from paper_1608_04721_amd import _lib
+    assert lib.pbf_set_memory_limit(-1) == _lib.PBF_ERR_INVALID_ARG
+    assert lib.pbf_set_memory_limit(1 << 20) == _lib.PBF_OK
+    assert lib.pbf_set_memory_limit(0) == _lib.PBF_OK
+    assert lib.pbf_device_bytes() == 0
