@@ -78,7 +78,10 @@ def test_create_out_of_memory_returns_no_context(lib):
     p = make_params(sc)
     x = np.ascontiguousarray(sc.x0, np.float32)
     v = np.ascontiguousarray(sc.v0, np.float32)
-    for budget in (1, 4096, 1 << 20):
+    with _sim(sc):
+        need = lib.pbf_device_bytes() - held  # what one context of this scene holds
+    assert lib.pbf_device_bytes() == held and need > 4096
+    for budget in (1, 4096, need // 2, need - 1):
         lib.pbf_set_memory_limit(held + budget)
         ctx = ctypes.c_void_p()
         st = lib.pbf_create(ctypes.byref(p), x.ctypes.data, v.ctypes.data, 0, None, ctypes.byref(ctx))

@@ -14,7 +14,7 @@ import torch  # noqa: F401  (first import can be slow; keep it out of test timeo
 import oracle
 import scenes
 from parity import (compare_keys, key_ambiguous, neighbour_mismatch, pos_tol, ref_csr,
-                    ulp_sensitivity)
+                    ulp_sensitivity, ulp_spread_per_particle)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,13 +42,18 @@ def _lambda_tol(lam_ref):
 
 def _check_step(sc, sim, x_ref, v_ref, info, check_nbrs=True, nbr_sample=None, tol=None,
                 lam_extra=0.0):
+    # tol: one bound for every particle, or an (n,) array of per-particle bounds
     x = sim.positions().astype(np.float64)
     v = sim.velocities().astype(np.float64)
     tol = pos_tol(sc) if tol is None else tol
     ex = np.abs(x - x_ref).max() if sc.n else 0.0
-    ev = np.abs(v - v_ref).max() if sc.n else 0.0
-    assert ex <= tol, f"positions: {ex:.3e} > {tol:.1e}"
-    assert ev <= tol / float(sc.dt), f"velocities: {ev:.3e}"
+    if sc.n:
+        exi = np.abs(x - x_ref).max(axis=1)
+        evi = np.abs(v - v_ref).max(axis=1)
+        worst = int(np.argmax(exi - tol))
+        assert np.all(exi <= tol), \
+            f"positions: {exi[worst]:.3e} > {np.broadcast_to(tol, exi.shape)[worst]:.1e} at {worst}"
+        assert np.all(evi <= np.asarray(tol) / float(sc.dt)), f"velocities: {evi.max():.3e}"
     if info is None or sc.n == 0:
         return ex
     xs0 = info["xs_iter"][0]
@@ -458,8 +463,20 @@ def test_tank_1m_state_the_benchmark_times(steps):
         sim.step(1)
         sim.sync()
         st = sim.stats()
-        x_ref, v_ref, info = oracle.apbf_step(sc, x0, v0, trace=True)
-        err = _check_step(sc, sim, x_ref, v_ref, info, nbr_sample=sample)
-    print(f"tank after {steps} steps: max position error {err:.3e} (bound {pos_tol(sc):.1e}); "
+        # By now splash droplets with a handful of neighbours exist; one
+        # float32 ulp of input moves their exact positions by up to ~1e-3.
+        # Those particles (a few hundred of the 1M) get 4x their own measured
+        # spread; every other particle is held to the plain bound.
+        (x_ref, v_ref, info), sx, sl = ulp_spread_per_particle(sc, x0, v0)
+        tol = np.maximum(pos_tol(sc), 4.0 * sx)
+        loose = int(np.sum(4.0 * sx > pos_tol(sc)))
+        assert loose <= sc.n // 1000, f"{loose} ill-conditioned particles"
+        err = _check_step(sc, sim, x_ref, v_ref, info, nbr_sample=sample, tol=tol,
+                          lam_extra=4.0 * sl)
+        well = 4.0 * sx <= pos_tol(sc)
+        err_well = float(np.abs(sim.positions() - x_ref)[well].max())
+    print(f"tank after {steps} steps: max position error {err:.3e}; over the "
+          f"{int(well.sum())} well-conditioned particles {err_well:.3e} (bound {pos_tol(sc):.1e}); "
+          f"{loose} particles with a one-ulp spread above the bound (largest {sx.max():.2e}); "
           f"max neighbours {st['max_neighbours']}, largest stage {st['max_stage']} entries, "
           f"tiles staged from HBM {st['tiles_unstaged']} (step before: {st0['tiles_unstaged']})")
