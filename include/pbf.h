@@ -337,6 +337,23 @@ pbf_status pbf_set_state(pbf_ctx *ctx, const float *x, const float *v, int64_t s
  * call and kept until pbf_destroy. */
 pbf_status pbf_density(pbf_ctx *ctx, double *out, float *rho_rel, int32_t on_device);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * measure as pbf_density, same arguments, results bit-identical to it, but
+ * nothing is allocated.  Its work buffers live in one fixed device array
+ * of PBF_STATIC_SCRATCH_BYTES per GPU, part of the library's code object,
+ * held from the first use on that GPU until the process ends.  Needs
+ * n_total * (2 * nbr_stride + 36) + n_tiles * 1171 + about 4 KiB bytes
+ * (nbr_stride = neighbour capacity rounded up to 8; n_tiles = tiles of
+ * 4x4x4 cells over all scenes); a context that needs more gets
+ * PBF_ERR_INVALID_ARG and nothing is enqueued.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and give wrong results; the library itself
+ * orders nothing between them.  The array keeps the last call's contents;
+ * each call clears what must start at zero. */
+#define PBF_STATIC_SCRATCH_BYTES (64ll << 20)
+pbf_status pbf_density_noalloc(pbf_ctx *ctx, double *out, float *rho_rel, int32_t on_device);
+
 /* ---------------- differentiable rollout (training form) ---------------- */
 
 /* Advance every scene by n_steps >= 1 steps like pbf_step, keeping a device

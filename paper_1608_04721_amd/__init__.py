@@ -334,6 +334,24 @@ class Sim:
                     "pbf_density")
         return (out[0], out[1], rho) if per_particle else (out[0], out[1])
 
+    def density_noalloc(self, rho_out=None):
+        """The same measure through pbf_density_noalloc, which allocates no
+        device memory (its work space is a fixed per-GPU array).  rho_out:
+        None, a float32 host array or a CUDA tensor of n values, filled in
+        ID order.  Returns (mean, max)."""
+        out = (ctypes.c_double * 2)()
+        ptr, on_dev = None, 0
+        if rho_out is not None:
+            if isinstance(rho_out, np.ndarray):
+                assert rho_out.dtype == np.float32 and rho_out.size == self.n
+                ptr = rho_out.ctypes.data
+            else:
+                assert rho_out.is_cuda and rho_out.numel() == self.n and rho_out.is_contiguous()
+                ptr, on_dev = rho_out.data_ptr(), 1
+        self._check(self._lib.pbf_density_noalloc(self._ctx, out, ptr, on_dev),
+                    "pbf_density_noalloc")
+        return out[0], out[1]
+
     # ------------------------------------------------ differentiable rollout
     def rollout_forward(self, n_steps: int, ckpt_every: int = 1):
         """Advance n_steps steps, checkpointing every ckpt_every steps for a

@@ -21,6 +21,7 @@ PBF_MAX_ITERS = 32
 PBF_MAX_CELL = 4096
 PBF_DEFAULT_NEIGHBOURS = 96
 PBF_MAX_SCENES = 65535
+PBF_STATIC_SCRATCH_BYTES = 64 << 20
 
 PBF_LOD_UNIFORM = 0
 PBF_LOD_EXPLICIT = 1
@@ -109,6 +110,7 @@ SIGNATURES = {
     "pbf_get_state": (c_i32, [CTX, c_vp, c_vp, P(c_i64)]),
     "pbf_set_state": (c_i32, [CTX, c_vp, c_vp, c_i64]),
     "pbf_density": (c_i32, [CTX, c_vp, c_vp, c_i32]),
+    "pbf_density_noalloc": (c_i32, [CTX, c_vp, c_vp, c_i32]),
     "pbf_rollout_forward": (c_i32, [CTX, c_i32, c_i32]),
     "pbf_rollout_backward": (c_i32, [CTX, c_vp, c_vp, c_vp, c_vp, c_i32]),
 }

@@ -382,6 +382,117 @@ pbf_status d2h(pbf_ctx *c, std::vector<T> &dst, const T *src, size_t count)
     return PBF_OK;
 }
 
+// Work space of pbf_density_noalloc: one fixed array per GPU (this code
+// object's copy on each device), so that entry point allocates nothing.
+// Host code never uses the array's name as an address: static_scratch gives
+// the device address, looked up once per device.
+constexpr long long kStaticScratchBytes = PBF_STATIC_SCRATCH_BYTES;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[PBF_STATIC_SCRATCH_BYTES];
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (made current for the lookup).
+hipError_t static_scratch(int device, unsigned char **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (prev != device) {
+            hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!q) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = (unsigned char *)q;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// Carve the density buffers of context c out of the work space at `base`
+// (256-byte aligned pieces); returns the bytes needed.  base = nullptr only
+// sizes.
+size_t static_density_layout(const pbf_ctx *c, unsigned char *base, DensityBuffers &d,
+                             float *&rho_stage)
+{
+    const size_t n = (size_t)c->n_total, T = c->b.n_tiles;
+    const size_t parts = (T + kXcds - 1) / kXcds * kXcds;
+    size_t off = 0;
+    auto take = [&](auto **ptr, size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        *ptr = base ? (std::remove_reference_t<decltype(*ptr)>)(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(**ptr);
+    };
+    take(&d.xs, n);
+    take(&d.key, n);
+    take(&d.nbr, n * (size_t)(c->b.nbr_stride / 8));
+    take(&d.pmeta, n);
+    take(&d.pslot, n);
+    take(&d.tile_rows, T * kRowWords);
+    take(&d.tile_order, T);
+    take(&d.tile_start, T + 1);
+    take(&d.tile_count, T);
+    take(&d.tile_ge, (size_t)PBF_MAX_ITERS + 2);
+    take(&d.tile_lvl, T);
+    take(&d.err, 1);
+    take(&d.totals, 2);
+    take(&d.rho_slot, n);
+    take(&d.part_sum, parts);
+    take(&d.part_max, parts);
+    take(&rho_stage, n);
+    take(&d.out, 2);
+    return off;
+}
+
+__global__ void k_clear_words(uint32_t *__restrict__ p, uint32_t count)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+// Zero `count` words on stream s with a kernel (no memset node).
+hipError_t clear_words(uint32_t *p, uint32_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_words, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+// The density measure with its buffers in d (err already cleared on the
+// stream): enqueue, copy the results out, synchronise, report faults.
+// rho_stage: n floats of device memory for a host rho_rel.
+pbf_status density_run(pbf_ctx *c, const DensityBuffers &d, float *rho_stage, double *out,
+                       float *rho_rel, int32_t on_device)
+{
+    const int64_t n = c->n_total;
+    float *rho_id = rho_rel ? (on_device ? rho_rel : rho_stage) : nullptr;
+    HIPCHK(c, enqueue_density(c->b, c->cur, c->ls, d, rho_id, c->stream), "density");
+    uint32_t bad = 0;
+    HIPCHK(c, hipMemcpyAsync(out, d.out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+           "density out");
+    HIPCHK(c, hipMemcpyAsync(&bad, d.err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
+           "density faults");
+    if (rho_rel && !on_device)
+        HIPCHK(c, hipMemcpyAsync(rho_rel, rho_id, (size_t)n * sizeof(float), hipMemcpyDeviceToHost,
+                                 c->stream),
+               "density out");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (bad & ERR_NEIGHBOUR_CAP)
+        return fail(c, PBF_ERR_CAPACITY, "pbf_density: a particle exceeded the neighbour capacity");
+    if (bad & ERR_CELL_CAP)
+        return fail(c, PBF_ERR_CAPACITY, "pbf_density: a cell or staged row exceeded its capacity");
+    return latched(c);
+}
+
 pbf_status step_n(pbf_ctx *c, int32_t n_steps);
 
 pbf_status need_step(pbf_ctx *c)
@@ -1131,24 +1242,36 @@ pbf_status pbf_density(pbf_ctx *c, double *out, float *rho_rel, int32_t on_devic
         d = nd;
         c->dens_rho_id = rho_id_buf;
     }
-    float *rho_id = rho_rel ? (on_device ? rho_rel : c->dens_rho_id) : nullptr;
     HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), c->stream), "clear faults");
-    HIPCHK(c, enqueue_density(c->b, c->cur, c->ls, d, rho_id, c->stream), "density");
-    uint32_t bad = 0;
-    HIPCHK(c, hipMemcpyAsync(out, d.out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
-           "density out");
-    HIPCHK(c, hipMemcpyAsync(&bad, d.err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
-           "density faults");
-    if (rho_rel && !on_device)
-        HIPCHK(c, hipMemcpyAsync(rho_rel, rho_id, (size_t)n * sizeof(float), hipMemcpyDeviceToHost,
-                                 c->stream),
-               "density out");
-    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
-    if (bad & ERR_NEIGHBOUR_CAP)
-        return fail(c, PBF_ERR_CAPACITY, "pbf_density: a particle exceeded the neighbour capacity");
-    if (bad & ERR_CELL_CAP)
-        return fail(c, PBF_ERR_CAPACITY, "pbf_density: a cell or staged row exceeded its capacity");
-    return latched(c);
+    return density_run(c, d, c->dens_rho_id, out, rho_rel, on_device);
+}
+
+pbf_status pbf_density_noalloc(pbf_ctx *c, double *out, float *rho_rel, int32_t on_device)
+{
+    if (!c || !out) return PBF_ERR_INVALID_ARG;
+    pbf_status st = need_step(c);
+    if (st != PBF_OK) return st;
+    const int64_t n = c->n_total;
+    if (n == 0) {
+        out[0] = out[1] = 0.0;
+        return PBF_OK;
+    }
+    DensityBuffers d{};
+    float *rho_stage = nullptr;
+    const size_t need = static_density_layout(c, nullptr, d, rho_stage);
+    if (need > (size_t)kStaticScratchBytes) {
+        char msg[192];
+        std::snprintf(msg, sizeof msg,
+                      "pbf_density_noalloc: needs %zu bytes of work space, the static array "
+                      "holds %lld",
+                      need, (long long)kStaticScratchBytes);
+        return fail(c, PBF_ERR_INVALID_ARG, msg);
+    }
+    unsigned char *base = nullptr;
+    HIPCHK(c, static_scratch(c->device, &base), "static scratch address");
+    static_density_layout(c, base, d, rho_stage);
+    HIPCHK(c, clear_words(d.err, 1, c->stream), "clear faults");
+    return density_run(c, d, rho_stage, out, rho_rel, on_device);
 }
 
 pbf_status pbf_debug_levels(pbf_ctx *c, uint8_t *levels)

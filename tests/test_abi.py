@@ -100,6 +100,8 @@ def test_null_arguments_rejected(lib):
     assert lib.pbf_sync(None) == _lib.PBF_ERR_INVALID_ARG
     assert lib.pbf_read_positions(None, None, 0) == _lib.PBF_ERR_INVALID_ARG
     assert lib.pbf_set_graph(None, 1) == _lib.PBF_ERR_INVALID_ARG
+    assert lib.pbf_density(None, None, None, 0) == _lib.PBF_ERR_INVALID_ARG
+    assert lib.pbf_density_noalloc(None, None, None, 0) == _lib.PBF_ERR_INVALID_ARG
     lib.pbf_destroy(None)
 
 
