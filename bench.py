@@ -39,6 +39,14 @@ FLOP_PER_PAIR = {"lambda": 26.0, "update": 21.0}
 # compulsory HBM bytes per active particle: lambda reads x* (16) and
 # writes lambda (4); update reads x* and lambda (16 + 4) and writes x* (16)
 BYTES_PER_ACTIVE = {"lambda": 20.0, "update": 36.0}
+# bytes the kernel design moves per active particle-iteration besides the
+# 16-byte neighbour-code groups (counted exactly, per group): metadata and
+# slot 8, the result (lambda 4, position 16), and the particle's share of
+# its tile's LDS stage, 6^3 cells staged for 4^3 own cells at 16 bytes an
+# entry (3.375 x 16 = 54)
+DESIGN_BYTES = {"lambda": {"per_active": 8.0 + 4.0 + 54.0},
+                "update": {"per_active": 8.0 + 16.0 + 54.0}}
+NBR_CAP = 256  # neighbour capacity of every tank run (APBF, DTVS, PBF): like for like
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3  # published vector FP32 peak (counts dual-issue)
 
@@ -56,19 +64,6 @@ def kernel_sources_digest() -> str:
         h.update(name.encode())
         h.update((csrc / name).read_bytes())
     return h.hexdigest()
-
-
-def _traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from the committed counter runs
-    (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy), or None when
-    the kernel sources have changed since they were taken."""
-    try:
-        rec = json.loads(TRAFFIC_FILE.read_text())
-    except (OSError, ValueError):
-        return None
-    if rec.get("sources_sha1") != kernel_sources_digest():
-        return None
-    return rec.get("bytes_per_dispatch", {}).get(kernel)
 
 
 def _timed_run(sim, steps, warmup, stream, torch):
@@ -98,15 +93,17 @@ def _timed_run(sim, steps, warmup, stream, torch):
             "density": {"mean_rho_over_rho0": round(mean_rho, 6), "max_rho_over_rho0": round(max_rho, 6)}}
 
 
-def _profile(sc, steps, Sim, stream):
+def _profile(sc, steps, Sim, stream, cap):
     """Per-kernel HIP-event timings over `steps` direct-launch steps, plus
-    the exact pair counts of every lambda/update launch."""
-    sim = Sim(sc, stream=stream)
+    the exact pair counts of every lambda/update launch and the bytes the
+    kernel design moves for them (see DESIGN_BYTES)."""
+    sim = Sim(sc, stream=stream, max_neighbours=cap)
     sim.step(2)  # same warm start as the timed run's graphs
     sim.sync()
     sim.profile_enable(True)
     pairs = {"lambda": 0, "update": 0}
     active = {"lambda": 0, "update": 0}
+    groups = 0
     launches = 0
     for _ in range(steps):
         sim.step(1)
@@ -119,48 +116,75 @@ def _profile(sc, steps, Sim, stream):
             pairs["update"] += int(cnt[act].sum())
             active["lambda"] += int(act.sum())
             active["update"] += int(act.sum())
+            groups += int(((cnt[act] + 7) // 8).sum())
         launches += K
     prof = sim.profile_read()
     sim.close()
-    return prof, pairs, active, launches
+    design = {k: DESIGN_BYTES[k]["per_active"] * active[k] + 16.0 * groups
+              for k in ("lambda", "update")}
+    return prof, pairs, active, launches, design
 
 
-def _roofline(prof, pairs, active):
+def _counters(kernel, avg_s):
+    """HBM traffic and VALU issue share of `kernel` from the committed
+    counter runs (None when the kernel sources have changed since)."""
+    try:
+        rec = json.loads(TRAFFIC_FILE.read_text())
+    except (OSError, ValueError):
+        return None, None, None
+    if rec.get("sources_sha1") != kernel_sources_digest():
+        return None, None, None
+    t = rec.get("bytes_per_dispatch", {}).get(kernel)
+    v = rec.get("valu_issue", {}).get(kernel)
+    return t, (round(t / rec["dispatch_s"][kernel] / 1e9 / PEAK_HBM_GBS, 4)
+               if t and rec.get("dispatch_s", {}).get(kernel) else None), v
+
+
+def _roofline(prof, pairs, active, design):
     tot = {k: v[0] for k, v in prof.items()}
     dom = max(("lambda", "update"), key=lambda k: tot[k])
     ms, n_launch = prof[dom]
     avg_s = ms * 1e-3 / n_launch
     flops = FLOP_PER_PAIR[dom] * pairs[dom] / n_launch
     bytes_ = BYTES_PER_ACTIVE[dom] * active[dom] / n_launch
+    dbytes = design[dom] / n_launch
     tflops = flops / avg_s / 1e12
     gbs = bytes_ / avg_s / 1e9
     f_alu, f_hbm = tflops / PEAK_FP32_TFLOPS, gbs / PEAK_HBM_GBS
+    traffic, hbm_frac, valu = _counters(dom, avg_s)
     if f_alu >= f_hbm:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(f_alu, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(f_hbm, 4)}
-    roof.update({"kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+    roof.update({"traffic": traffic, "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
                  "algorithmic_bytes_per_launch": int(bytes_),
                  "algorithmic_flop_per_launch": int(flops),
-                 "hbm_model_gbs": round(gbs, 1), "alu_tflops": round(tflops, 3),
-                 "traffic": _traffic(dom)})
+                 "design_bytes_per_launch": int(dbytes),
+                 "hbm_model_gbs": round(gbs, 1), "design_model_gbs": round(dbytes / avg_s / 1e9, 1),
+                 "alu_tflops": round(tflops, 3),
+                 "counter_hbm_frac": hbm_frac, "valu_issue_share": valu})
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1],
                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
                for k, v in prof.items() if v[1]}
     return roof, kernels
 
 
-def _cpu_baseline(sc, steps):
-    import oracle
-    oracle.build(force=False)
+def _cpu_model() -> str:
     try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    oracle.set_threads(cores)
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(sc, steps, threads):
+    import oracle
+    oracle.set_threads(threads)
     x, v = sc.x0.astype(np.float64), sc.v0.astype(np.float64)
     pit = 0
     t0 = time.perf_counter()
@@ -169,11 +193,67 @@ def _cpu_baseline(sc, steps):
         pit += int(lv.sum())
         x, v, _ = oracle.apbf_step(sc, x, v)
     dt = time.perf_counter() - t0
-    return {"value": round(pit / dt, 1), "unit": "particle-iterations/s",
-            "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"first {steps} steps of the same 1,048,576-particle APBF workload "
-                      f"from the same initial state ({dt:.1f} s)",
-            "ms_per_step": round(1e3 * dt / steps, 1)}
+    return pit / dt, dt, oracle.get_threads()
+
+
+def _cpu_baseline(sc, steps, steps_1t=1):
+    """The FP64 oracle on the host: every core (up to 16) over the first
+    `steps` steps, and one thread over the first `steps_1t` steps, of the
+    same workload from the same initial state."""
+    import oracle
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    rate, dt, used = _oracle_rate(sc, steps, cores)
+    out = {"value": round(rate, 1), "unit": "particle-iterations/s",
+           "cores": used, "kind": "oracle",
+           "sample": f"first {steps} steps of the same {sc.n:,}-particle APBF workload "
+                     f"from the same initial state ({dt:.1f} s)",
+           "ms_per_step": round(1e3 * dt / steps, 1), "cpu_model": _cpu_model()}
+    if steps_1t:
+        rate1, dt1, _ = _oracle_rate(sc, steps_1t, 1)
+        out["one_thread"] = {"value": round(rate1, 1), "ms_per_step": round(1e3 * dt1 / steps_1t, 1),
+                             "sample": f"first {steps_1t} step(s), 1 thread ({dt1:.1f} s)"}
+    return out
+
+
+def _full_run(sc, steps, Sim, stream, torch, cap, **kw):
+    """`steps` graph-replayed steps from the scene's initial state, timed as
+    a whole with HIP events on the context stream; a device fault is
+    reported with the first step that raised it (found again untimed, one
+    synchronised step at a time)."""
+    from paper_1608_04721_amd import PbfError
+    with Sim(sc, stream=stream, max_neighbours=cap, **kw) as sim:
+        sim.set_graph(True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        try:
+            sim.sync()
+        except PbfError as err:
+            msg = str(err)
+        else:
+            ms = e0.elapsed_time(e1)
+            st = sim.stats()
+            pit = st["total_particle_iterations"]
+            return {"steps": steps, "ms_per_step": round(ms / steps, 4),
+                    "value": round(pit / (ms * 1e-3), 1),
+                    "mean_levels": round(pit / (steps * sim.n), 4),
+                    "max_neighbours_last_step": st["max_neighbours"]}
+    with Sim(sc, stream=stream, max_neighbours=cap, **kw) as sim:
+        sim.set_graph(True)
+        for k in range(1, steps + 1):
+            sim.step(1)
+            try:
+                sim.sync()
+            except PbfError:
+                return {"steps": steps, "error": msg, "first_fault_step": k}
+    return {"steps": steps, "error": msg}
 
 
 def run_batch(args, torch, stream):
@@ -415,9 +495,14 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=5)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps-1t", type=int, default=1,
+                    help="steps of the one-thread oracle rate (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-pbf", action="store_true", help="skip the PBF(10)/PBF(5) runs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 100-step runs, the 262k dam break, the batch and the rollout")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -446,10 +531,11 @@ def main(argv=None):
         return 0
     sc = scenes.tank_1m()
     steps, warm = args.steps, args.warmup
+    cap = NBR_CAP
 
     print(f"[bench] APBF {sc.name}: n={sc.n}, levels {sc.n_min}..{sc.n_max}", file=sys.stderr,
           flush=True)
-    with Sim(sc, stream=stream) as sim:
+    with Sim(sc, stream=stream, max_neighbours=cap) as sim:
         apbf = _timed_run(sim, steps, warm, stream, torch)
     # the same tank with distance-to-the-visible-surface levels (the paper's
     # second adaption model), seen from the same camera
@@ -457,7 +543,7 @@ def main(argv=None):
     # t = 0, close to the distance-to-camera run's 7.4)
     scv = scenes.with_dtvs(sc, camera=sc.camera, target=(3.2, 1.6, 3.2), d_far=4.0)
     print("[bench] APBF with visible-surface levels", file=sys.stderr, flush=True)
-    with Sim(scv, stream=stream) as sim:
+    with Sim(scv, stream=stream, max_neighbours=cap) as sim:
         try:
             dtvs = _timed_run(sim, steps, warm, stream, torch)
         except PbfError as e:
@@ -468,20 +554,52 @@ def main(argv=None):
             scp = sc.with_lod(PBF_LOD_UNIFORM, n_min=N, n_max=N)
             print(f"[bench] PBF N={N}", file=sys.stderr, flush=True)
             # plain PBF with few iterations may compress this deep tank far
-            # beyond rest density; a larger neighbour capacity lets it finish
-            # and the fault, if any, is reported instead of ending the run
-            with Sim(scp, stream=stream, max_neighbours=256) as sim:
+            # beyond rest density; a fault is reported instead of ending the run
+            with Sim(scp, stream=stream, max_neighbours=cap) as sim:
                 try:
                     out_pbf[N] = _timed_run(sim, steps, warm, stream, torch)
                 except PbfError as e:
                     out_pbf[N] = {"error": str(e)}
     print("[bench] profiling kernels", file=sys.stderr, flush=True)
-    prof, pairs, active, _ = _profile(sc, args.profile_steps, Sim, stream)
-    roof, kernels = _roofline(prof, pairs, active)
+    prof, pairs, active, _, design = _profile(sc, args.profile_steps, Sim, stream, cap)
+    roof, kernels = _roofline(prof, pairs, active, design)
+    extra = {}
+    if not args.no_extra:
+        # the stated 100-step runs from t = 0, like for like (same capacity)
+        full = {}
+        for name, s_ in (("apbf", sc), ("pbf10", sc.with_lod(PBF_LOD_UNIFORM, n_min=10, n_max=10)),
+                         ("pbf5", sc.with_lod(PBF_LOD_UNIFORM, n_min=5, n_max=5))):
+            print(f"[bench] {name}: {sc.steps} steps from t = 0", file=sys.stderr, flush=True)
+            full[name] = _full_run(s_, int(sc.steps), Sim, stream, torch, cap)
+        if "error" not in full["apbf"] and "error" not in full["pbf10"]:
+            full["speedup_vs_pbf10"] = round(full["pbf10"]["ms_per_step"] / full["apbf"]["ms_per_step"], 4)
+        extra["tank_1m_100_steps"] = full
+        # the 262,144-particle dam break, plain PBF with N = 10, 100 steps
+        sd = scenes.dam_break_262k()
+        print(f"[bench] {sd.name}: {sd.steps} steps", file=sys.stderr, flush=True)
+        r = _full_run(sd, int(sd.steps), Sim, stream, torch, cap)
+        r["workload"] = ("dam_break_262k: 262,144 particles (64^3 lattice) in the corner of a "
+                         "12.8x6.4x6.4 tank, plain PBF N=10, dt=1/120, 100 steps from t = 0")
+        extra["dam_break_262k"] = r
+        # 64 batched scenes against 64 serial contexts
+        nb = argparse.Namespace(steps=args.batch_steps, warmup=3)
+        b = run_batch(nb, torch, stream)
+        extra["batch_64"] = {"particles": b["config"]["particles"], "steps": b["steps"],
+                             "ms_per_step": b["ms_per_step"], "value": b["value"],
+                             "serial_ms_per_step": b["serial"]["ms_per_step"],
+                             "speedup_vs_serial": b["speedup_vs_serial"],
+                             "block_sizes": b["config"]["block_sizes"]}
+        # reverse mode against the forward rollout, 32k particles, 20 steps
+        ro = run_rollout(argparse.Namespace(steps=20), torch, stream)
+        extra["rollout_32k"] = {"adjoint_vs_forward": ro["value"],
+                                "ms_rollout_forward": ro["ms_rollout_forward"],
+                                "ms_rollout_backward": ro["ms_rollout_backward"],
+                                "ms_forward_plain_graph": ro["ms_forward_plain_graph"],
+                                "backward_vs_plain_forward": ro["backward_vs_plain_forward"]}
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
-        cpu = _cpu_baseline(sc, args.cpu_steps)
+        cpu = _cpu_baseline(sc, args.cpu_steps, args.cpu_steps_1t)
 
     line = {
         "metric": METRIC,
@@ -500,7 +618,7 @@ def main(argv=None):
                                "h=0.1, v~N(0,0.1^2)), box 6.4^3, distance-to-camera levels "
                                "5..10, dt=1/120",
                    "particles": sc.n, "levels": [sc.n_min, sc.n_max], "lod": "dtc",
-                   "launch": "hipGraph per step"},
+                   "launch": "hipGraph per step", "neighbour_capacity": cap},
         "ms_median": round(apbf["ms_median"], 4),
         "mean_levels": round(apbf["mean_levels"], 4),
         "roofline": roof,
@@ -528,6 +646,7 @@ def main(argv=None):
                 line[f"speedup_vs_pbf{N}"] = round(out_pbf[N]["ms_per_step"] / apbf["ms_per_step"], 4)
         if "error" not in out_pbf[10] and "error" not in dtvs:
             line["dtvs"]["speedup_vs_pbf10"] = round(out_pbf[10]["ms_per_step"] / dtvs["ms_per_step"], 4)
+    line.update(extra)
     print(json.dumps(line), flush=True)
     return 0
 

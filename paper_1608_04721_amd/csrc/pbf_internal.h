@@ -152,7 +152,8 @@ __device__ __forceinline__ bool split_part(uint32_t nown, uint32_t sub, uint32_t
 
 // Every buffer one step touches.  Storage ("slot") order is the cell order
 // of the last counting sort.  Per-particle solver data ("p" order) is laid
-// out tile by tile: p = tile_start[tile] + own index inside the tile.
+// out tile by tile: p = tile_start[tile] + rank inside the tile (descending
+// level, ties in cell order), so each iteration's active particles come first.
 struct StepBuffers {
     int64_t n;               // particles, all scenes
     uint32_t n_cells;        // cells, all scenes

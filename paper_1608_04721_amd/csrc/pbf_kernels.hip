@@ -12,7 +12,8 @@
 //               particle counts, tile_order lists them by descending largest
 //               level, so the tiles holding active particles of iteration k
 //               are a prefix of tile_order (Eqs. 9-10: the active sets nest)
-//   nbr         neighbour codes in p order (p = tile_start[tile] + own index),
+//   nbr         neighbour codes in p order (p = tile_start[tile] + the
+//               particle's rank in its tile by descending level, see rank_part),
 //               u16 codes packed eight per 16-byte group, group-major:
 //               group g of particle p at [g * n + p]; a code is the
 //               neighbour's index in the tile's LDS stage, or row << 10 |
@@ -1100,6 +1101,91 @@ __global__ __launch_bounds__(1024) void k_tile_tables(
     }
 }
 
+// Order of the own particles of a tile part in p (the order of the solver
+// passes): by descending level, ties in cell order.  The active particles
+// of every iteration then form a prefix of the part (Eqs. 9-10), so
+// finished particles leave whole waves idle rather than single lanes.  Each
+// particle's sums keep their neighbour-list order, so no result depends on
+// this order.
+//
+// A stable counting sort by level, before the stage is loaded (its LDS is
+// the scratch): each wave counts the levels of each round of blockDim.x
+// particles by ballots, and a particle's rank is the number of particles
+// of higher level in the part, plus those of its level in earlier rounds
+// and waves, plus those below it in its wave.  Parts of more than kRankHold
+// * blockDim.x particles keep cell order.
+constexpr int kRankHold = 4;  // particles per thread that carry a rank
+constexpr int kRankWaves = kNbrThreads / 64;
+constexpr int kRankLevels = PBF_MAX_ITERS + 1;
+struct RankLds {
+    uint32_t count[kRankHold][kRankWaves][kRankLevels];  // particles per round, wave and level
+    uint32_t above[kRankLevels];  // particles of the part with a higher level
+};
+
+// Slot of own particle pl of a tile (cell order) and its staged row.
+__device__ __forceinline__ uint32_t own_slot(const TileTables &tb, uint32_t pl, int &row)
+{
+    int o = 0;
+    while (tb.own[o + 1] <= pl) ++o;
+    row = (1 + o / kTileEdge) * kStageEdge + (1 + o % kTileEdge);
+    return tb.bnd[row][1] + (pl - tb.own[o]);
+}
+
+// rank[q]: position in the part of own particle first + threadIdx.x + q *
+// blockDim.x (all threads call; ends with a barrier).
+__device__ void rank_part(RankLds &L, const TileTables &tb, uint32_t first, uint32_t m,
+                          const uint8_t *__restrict__ lvl, uint32_t (&rank)[kRankHold])
+{
+    const uint32_t bd = blockDim.x, t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6, nw = (int)(bd >> 6);
+    const int rounds = (int)((m + bd - 1) / bd);  // <= kRankHold
+    for (uint32_t e = t; e < (uint32_t)(kRankHold * kRankWaves * kRankLevels); e += bd)
+        (&L.count[0][0][0])[e] = 0u;
+    __syncthreads();
+    int lv[kRankHold];
+#pragma unroll
+    for (int q = 0; q < kRankHold; ++q) {
+        const uint32_t e = t + (uint32_t)q * bd;
+        int row;
+        lv[q] = e < m ? (int)lvl[own_slot(tb, first + e, row)] : -1;
+        rank[q] = 0;
+        if (q >= rounds) continue;  // uniform
+        // rank inside the wave among equal levels; the lowest lane of each level counts
+        uint64_t rem = __ballot(lv[q] >= 0);
+        while (rem) {
+            const int f = __ffsll((unsigned long long)rem) - 1;
+            const int l0 = __shfl(lv[q], f, 64);
+            const uint64_t mm = __ballot(lv[q] == l0);
+            if (lv[q] == l0) rank[q] = (uint32_t)__popcll(mm & ((1ull << lane) - 1ull));
+            if (lane == f) L.count[q][wave][l0] = (uint32_t)__popcll(mm);
+            rem &= ~mm;
+        }
+    }
+    __syncthreads();
+    if (t < (uint32_t)kRankLevels) {  // particles of each level in the part, then those above it
+        uint32_t tot = 0;
+        for (int q = 0; q < rounds; ++q)
+            for (int w = 0; w < nw; ++w) tot += L.count[q][w][t];
+        uint32_t suf = tot;  // suffix sum over the levels (lanes 0..32 of wave 0)
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_down(suf, o, 64);
+            if (lane + o < kRankLevels) suf += u;
+        }
+        L.above[t] = suf - tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRankHold; ++q) {
+        if (lv[q] < 0) continue;
+        uint32_t r = L.above[lv[q]] + rank[q];
+        for (int q2 = 0; q2 <= q; ++q2)
+            for (int w = 0; w < (q2 < q ? nw : wave); ++w) r += L.count[q2][w][lv[q]];
+        rank[q] = r;
+    }
+    __syncthreads();  // the stage may overwrite the tables now
+}
+
 // ------------------------------------------------------ neighbour lists
 // N_i = { j != i : |x*_i - x*_j|^2 < h^2 } over the 27 cells around x*_i
 // (Fig. 7 second loop), kept for every iteration of the step.  The 27 cells
@@ -1124,19 +1210,23 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                                                     int64_t n, int cap, const uint8_t *__restrict__ lvl,
                                                     uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta,
                                                     uint32_t *__restrict__ pslot, uint32_t first,
-                                                    uint32_t last)
+                                                    uint32_t last, uint32_t rank01, uint32_t rank23)
 {
     uint32_t bad = 0;
-    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
-        int o = 0;
-        while (tb.own[o + 1] <= pl) ++o;
-        const int sy = 1 + o % kTileEdge, sz = 1 + o / kTileEdge;
-        const int r = sz * kStageEdge + sy;
-        const uint32_t i = tb.bnd[r][1] + (pl - tb.own[o]);
+    uint32_t q = 0;
+    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x, ++q) {
+        int r;
+        const uint32_t i = own_slot(tb, pl, r);
+        const int sy = r % kStageEdge, sz = r / kStageEdge;
+        // position in the part: its rank (see rank_part), two 16-bit ranks
+        // per word for the thread's first four particles
+        const uint32_t pr = q < 2u ? ((q ? rank01 >> 16 : rank01) & 0xffffu)
+                            : q < 4u ? ((q & 1u ? rank23 >> 16 : rank23) & 0xffffu)
+                                     : pl - first;
         int lx = 1;
         while (lx < kTileEdge && tb.bnd[r][lx + 1] <= i) ++lx;  // x-cell of i, 1..kTileEdge
         const float4 xi = FITS ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
-        const size_t p = p0 + pl;
+        const size_t p = (size_t)p0 + first + pr;
         uint32_t cnt = 0;
         const uint32_t cap8 = ((uint32_t)cap + 7u) & ~7u;  // codes that have room
         // each code is stored as it is found, 16 bits at a time; the pointer
@@ -1232,13 +1322,27 @@ __global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(8))
             rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
     const float h2 = t.S->h2;
     const uint32_t p0 = tile_start[tile];
+    // positions of the own particles in the part (uniform condition); the
+    // stage array is the scratch of the ranking until it is loaded
+    uint32_t rank[kRankHold];
+    const uint32_t m = last - first;
+    if (m > 1u && m <= (uint32_t)kRankHold * blockDim.x) {
+        static_assert(sizeof(RankLds) <= sizeof(stage), "ranking tables fit in the stage array");
+        rank_part(*reinterpret_cast<RankLds *>(stage), tb, first, m, lvl, rank);
+    } else {
+#pragma unroll
+        for (int q = 0; q < kRankHold; ++q) rank[q] = threadIdx.x + (uint32_t)q * blockDim.x;
+    }
+    static_assert(kRankHold == 4 && kRankHold * kNbrThreads <= 65536, "ranks packed two per word");
+    const uint32_t rank01 = rank[0] | (rank[1] << 16), rank23 = rank[2] | (rank[3] << 16);
     uint32_t bad;
     if (fits) {
         tile_stage(tb, xs, stage);
-        bad = tile_neighbours<true>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot, first, last);
+        bad = tile_neighbours<true>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot, first, last,
+                                    rank01, rank23);
     } else {
         bad = tile_neighbours<false>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot, first,
-                                     last);
+                                     last, rank01, rank23);
     }
     if (bad) atomicOr(err, bad);
 }
@@ -1277,8 +1381,11 @@ __device__ __forceinline__ void for_each_neighbour(const TileTables &tb,
     // loaded while this group is evaluated; the index is clamped to the last
     // group (group 0 exists for every p), so every load is unconditional
     const uint32_t last = cnt ? (cnt - 1u) >> 3 : 0u;
+    const uint32_t stride = (uint32_t)n;  // groups of one particle are n entries apart
+    const uint4 *__restrict__ gp = nbr + p + (last ? stride : 0u);  // group min(1, last)
     for (uint32_t q = 0; q < cnt; q += 8) {
-        const uint4 vn = nbr[(size_t)min((q >> 3) + 1u, last) * n + p];
+        const uint4 vn = *gp;
+        gp += (q >> 3) + 2u <= last ? stride : 0u;
         const uint32_t cc[8] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16,
                                 v.z & 0xffffu, v.z >> 16, v.w & 0xffffu, v.w >> 16};
         v = vn;
@@ -1334,7 +1441,16 @@ __device__ __forceinline__ Head load_head(const uint32_t *__restrict__ pmeta,
 }
 
 // lambda_i for the active own particles of a tile (Eqs. 4-6)
-template <bool FITS, bool WIDE>
+// UNIT: h <= 1 (so h^2 - r^2 <= 1 and h - r <= 1), and the clamps at zero of
+// the pair terms become the clamp to [0, 1] of the instruction producing
+// them (one instruction less each).
+template <bool UNIT>
+__device__ __forceinline__ float pos_part(float v)
+{
+    return UNIT ? __builtin_amdgcn_fmed3f(v, 0.f, 1.f) : fmaxf(v, 0.f);
+}
+
+template <bool FITS, bool WIDE, bool UNIT>
 __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const TileTables &tb,
                                             const float4 *__restrict__ stage, float4 *__restrict__ xs,
                                             int64_t n, const uint4 *__restrict__ nbr,
@@ -1362,10 +1478,10 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
             if (WIDE) asm volatile("" : : "v"(xj.w));
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const float w = fmaxf(h2 - r2, 0.f);
+            const float w = pos_part<UNIT>(h2 - r2);
             sum6 += w * w * w;
             const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, kTinyR2));
-            const float hr = fmaxf(h - r2 * ir, 0.f);
+            const float hr = pos_part<UNIT>(h - r2 * ir);
             const float q = hr * hr * ir;  // grad W = -c_grad q d
             gx += q * dx;
             gy += q * dy;
@@ -1399,15 +1515,17 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
-    if (stage_rows(rows, tile, xs, tb, stage))
-        tile_lambda<true, !SPLIT>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
+    if (!stage_rows(rows, tile, xs, tb, stage))
+        tile_lambda<false, !SPLIT, false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
+    else if (S.h <= 1.f)
+        tile_lambda<true, !SPLIT, true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
     else
-        tile_lambda<false, !SPLIT>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
+        tile_lambda<true, !SPLIT, false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
 }
 
 // Delta p_i (Eq. 7) with the wall contact (clamp) for the active own
 // particles of a tile
-template <bool FITS, bool CONTACTS>
+template <bool FITS, bool CONTACTS, bool UNIT>
 __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const TileTables &tb,
                                             const float4 *__restrict__ stage,
                                             const float4 *__restrict__ xs_in,
@@ -1441,7 +1559,7 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
             const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, kTinyR2));
-            const float hr = fmaxf(h - r2 * ir, 0.f);
+            const float hr = pos_part<UNIT>(h - r2 * ir);
             const float f = hr * hr * ir * (li + xj.w);  // (lambda_i + lambda_j) grad W = -c_grad f d
             px += f * dx;
             py += f * dy;
@@ -1481,12 +1599,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
-    if (stage_rows(rows, tile, xs_in, tb, stage))
-        tile_update<true, CONTACTS>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact, p0,
-                                    nown, first, last, hd);
+    if (!stage_rows(rows, tile, xs_in, tb, stage))
+        tile_update<false, CONTACTS, false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact,
+                                            p0, nown, first, last, hd);
+    else if (S.h <= 1.f)
+        tile_update<true, CONTACTS, true>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact,
+                                          p0, nown, first, last, hd);
     else
-        tile_update<false, CONTACTS>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact, p0,
-                                     nown, first, last, hd);
+        tile_update<true, CONTACTS, false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact,
+                                           p0, nown, first, last, hd);
 }
 
 // ------------------------------------------------ average density
