@@ -483,6 +483,67 @@ def run_traffic(args, torch, stream):
             "neighbour_pairs_last_step": st["neighbour_pairs"]}
 
 
+VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 4 cycles each per SIMD
+COPY_BYTES = 256 << 20
+
+
+def summarize_counters(root: Path) -> dict:
+    """Per-kernel figures from the rocprofv3 passes over `--workload
+    traffic` under `root` (sub-folders fetch, write, sq1, sq2 with their
+    *_counter_collection.csv): HBM bytes per dispatch calibrated by the
+    256 MiB copy of the same run, the VALU issue share, the LDS bank
+    conflict ratio and the wait share."""
+    import collections
+    import csv
+    import re
+
+    def short(name):
+        m = re.search(r"(k_\w+)", name)
+        return m.group(1).replace("k_", "", 1) if m else name.split("(")[0]
+
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(dict)  # kernel -> dispatch -> seconds
+    copies = collections.defaultdict(list)
+    for sub in ("fetch", "write", "sq1", "sq2"):
+        files = sorted((root / sub).rglob("*counter_collection.csv"))
+        if not files:
+            continue
+        for r in csv.DictReader(open(files[0])):
+            k, c, v = short(r["Kernel_Name"]), r["Counter_Name"], float(r["Counter_Value"])
+            did = (sub, r["Dispatch_Id"])
+            t = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+            if c in ("FETCH_SIZE", "WRITE_SIZE") and "copyBuffer" in r["Kernel_Name"]:
+                copies[c].append(v)
+            per[k][c] += v
+            disp[k].setdefault(did, t)
+    out = {"fetch_factor": None, "write_factor": None, "bytes_per_dispatch": {}, "dispatch_s": {},
+           "valu_issue": {}, "lds_conflict_ratio": {}, "wait_share": {},
+           "sources_sha1": kernel_sources_digest()}
+    kib = COPY_BYTES / 1024
+    big_w = [v for v in copies["WRITE_SIZE"] if abs(v - kib) < 0.01 * kib]
+    big_f = sorted(copies["FETCH_SIZE"])[-len(big_w):] if big_w else []
+    if big_w and big_f:
+        out["write_factor"] = sum(big_w) / len(big_w) / kib
+        out["fetch_factor"] = sum(big_f) / len(big_f) / kib
+    for k, cs in per.items():
+        if not k or "copyBuffer" in k:
+            continue
+        n = {sub: sum(1 for (s_, _) in disp[k] if s_ == sub) for sub in ("fetch", "write", "sq1", "sq2")}
+        dur = {sub: sum(t for (s_, _), t in disp[k].items() if s_ == sub) for sub in n}
+        if n["fetch"] and n["write"] and out["fetch_factor"]:
+            out["bytes_per_dispatch"][k] = int(1024 * (cs["FETCH_SIZE"] / n["fetch"] / out["fetch_factor"] +
+                                                       cs["WRITE_SIZE"] / n["write"] / out["write_factor"]))
+            out["dispatch_s"][k] = dur["fetch"] / n["fetch"]
+        if n["sq1"] and cs.get("SQ_INSTS_VALU"):
+            out["valu_issue"][k] = round(cs["SQ_INSTS_VALU"] / dur["sq1"] / VALU_PEAK_WAVE_INSTR, 4)
+            if cs.get("SQ_WAVE_CYCLES") and n["sq2"]:
+                out["wait_share"][k] = round((cs["SQ_WAIT_INST_ANY"] / n["sq2"]) /
+                                             (cs["SQ_WAVE_CYCLES"] / n["sq1"]), 4)
+        if cs.get("SQ_ACTIVE_INST_LDS"):
+            out["lds_conflict_ratio"][k] = round(cs["SQ_LDS_BANK_CONFLICT"] / cs["SQ_ACTIVE_INST_LDS"], 3)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", choices=("tank", "batch", "rollout", "multidam", "traffic"),
@@ -503,7 +564,15 @@ def main(argv=None):
     ap.add_argument("--no-pbf", action="store_true", help="skip the PBF(10)/PBF(5) runs")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 100-step runs, the 262k dam break, the batch and the rollout")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write profiles/tank_1m_traffic.json from the rocprofv3 counter "
+                         "passes under DIR (fetch, write, sq1, sq2) and exit; no GPU needed")
     args = ap.parse_args(argv)
+    if args.summarize_counters:
+        rec = summarize_counters(Path(args.summarize_counters))
+        TRAFFIC_FILE.write_text(json.dumps(rec, indent=1, sort_keys=True) + "\n")
+        print(json.dumps(rec, indent=1, sort_keys=True))
+        return 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the solver has no multi-GPU path)",

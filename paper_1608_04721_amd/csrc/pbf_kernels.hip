@@ -1246,7 +1246,10 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
             const uint32_t ja = tb.bnd[r2][lx - 1], len = tb.bnd[r2][lx + 2] - ja;
             const uint32_t l0 = tb.base[r2] + (ja - g0);
             for (uint32_t c0 = 0; c0 < len; c0 += 32) {
-                // distance test of up to 32 candidates into a bit mask ...
+                // distance test of up to 32 candidates into a bit mask: the
+                // sign of |d|^2 - h^2 (h^2 folded into the first FMA) is
+                // shifted into the mask, one instruction per candidate, so
+                // the candidate tested last sits in bit 0 ...
                 const uint32_t cl = min(len - c0, 32u);
                 uint32_t m = 0;
                 for (uint32_t c = 0; c < cl; c += 4) {
@@ -1257,15 +1260,17 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
                         xj[u] = FITS ? sp[u] : xs[min((int64_t)(ja + c0 + c + u), n - 1)];
-                    uint32_t nib = 0;  // hits of the four, bit u
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         if (FITS) asm volatile("" : : "v"(xj[u].w));  // 16-byte LDS reads
                         const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
-                        nib |= (dx * dx + dy * dy + dz * dz < h2) ? (1u << u) : 0u;
+                        const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -h2)));  // < 0: inside
+                        m = __builtin_amdgcn_alignbit(m, __float_as_uint(e), 31);
                     }
-                    m |= nib << c;
                 }
+                // ... and reversed, so that candidate c is bit c
+                const uint32_t tested = (cl + 3u) & ~3u;
+                m = __builtin_bitreverse32(m) >> (32u - tested);
                 if (cl < 32u) m &= (1u << cl) - 1u;
                 if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1u << (i - ja - c0));  // not itself
                 // ... then its hits become codes, in candidate order

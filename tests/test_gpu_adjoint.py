@@ -289,3 +289,36 @@ def test_training_rollout_velocity_gradient():
         worst = max(worst, err)
         assert err <= tol, (an, fd)
     print(f"directional derivatives: worst error {worst:.2e} of |g|")
+
+
+def test_rollout_32k_stated_checkpointing():
+    """The stated reverse-mode configuration: 32,768 particles, N = 6, 20
+    steps with a checkpoint every 5 steps, so four segments are recomputed
+    from their checkpoints during the reverse pass.  The recomputed steps
+    are bit-identical to the recorded ones (ties of the counting sort are
+    broken by particle ID), so the gradient must equal, bit for bit, that of
+    one segment recorded whole; 10 steps every 5 against every step, and
+    every 3 (segments of uneven length), likewise.  (Against the oracle the
+    20-step gradient is not comparable element by element: a one-ulp change
+    of the input moves the oracle's own gradient by O(1) after 5 steps, and
+    the 3-step comparison is test_training_rollout_velocity_gradient.)"""
+    sc = scenes.rollout_32k()
+    n = sc.n
+    tgt = sc.target.astype(np.float64)
+
+    def grad(steps, every):
+        sim = _sim(sc)
+        sim.rollout_forward(steps, every)
+        xg = sim.positions().astype(np.float64)
+        g = ((2.0 / n) * (xg - tgt)).astype(np.float32)
+        gx, gv = sim.rollout_backward(g, np.zeros((n, 3), np.float32))
+        sim.close()
+        return gx, gv
+
+    a, b = grad(20, 5), grad(20, 20)
+    assert np.all(np.isfinite(a[0])) and np.all(np.isfinite(a[1]))
+    assert float(np.abs(a[1]).max()) > 0.0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    c, d, e = grad(10, 5), grad(10, 1), grad(10, 3)
+    for o in (d, e):
+        assert np.array_equal(c[0], o[0]) and np.array_equal(c[1], o[1])
