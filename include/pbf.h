@@ -343,7 +343,7 @@ pbf_status pbf_density(pbf_ctx *ctx, double *out, float *rho_rel, int32_t on_dev
  * nothing is allocated.  Its work buffers live in one fixed device array
  * of PBF_STATIC_SCRATCH_BYTES per GPU, part of the library's code object,
  * held from the first use on that GPU until the process ends.  Needs
- * n_total * (2 * nbr_stride + 36) + n_tiles * 1181 bytes plus at most 8 KiB
+ * n_total * (2 * nbr_stride + 36) + n_tiles * 1197 bytes plus at most 8 KiB
  * (nbr_stride = neighbour capacity rounded up to 8; n_tiles = tiles of
  * 4x4x4 cells over all scenes); a context that needs more gets
  * PBF_ERR_INVALID_ARG and nothing is enqueued.  Every call on one GPU

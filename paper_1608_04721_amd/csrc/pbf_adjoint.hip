@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kDecodeThreads) void k_adj_decode(
     uint32_t first, last;
     if (!split_part(nown, blockIdx.x / tiles, gridDim.x / tiles, first, last)) return;
     for (int e = threadIdx.x; e < kRowWords; e += blockDim.x) {
-        const uint32_t w = rows[(size_t)tile * kRowWords + e];
+        const uint32_t w = rows[(size_t)b * kRowWords + e];  // by slot
         if (e < kBndWords) bnd[e] = w;
         else base[e - kBndWords] = w;
     }

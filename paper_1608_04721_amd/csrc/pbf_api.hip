@@ -439,6 +439,7 @@ size_t static_density_layout(const pbf_ctx *c, unsigned char *base, DensityBuffe
     take(&d.pmeta, n);
     take(&d.pslot, n);
     take(&d.tile_rows, T * kRowWords);
+    take(&d.tile_rec, T);
     take(&d.tile_order, T);
     take(&d.tile_start, T + 1);
     take(&d.tile_count, T);
@@ -684,6 +685,7 @@ pbf_status pbf_batch_create(int32_t n_scenes, const pbf_params *params, const fl
     AL(b.tile_ge, (size_t)PBF_MAX_ITERS + 2);
     AL(b.tile_order, (size_t)tiles);
     AL(b.tile_rows, (size_t)tiles * kRowWords);
+    AL(b.tile_rec, (size_t)tiles);
     AL(b.nbr, n * (size_t)(b.nbr_stride / 8));
     AL(b.pmeta, n);
     AL(b.pslot, n);
@@ -1077,13 +1079,15 @@ pbf_status pbf_stats(pbf_ctx *c, pbf_step_stats *o)
         o->neighbour_pairs += cnt;
         o->max_neighbours = std::max(o->max_neighbours, cnt);
     }
-    // staged neighbourhood of every tile with particles (saved stage tables)
-    std::vector<uint32_t> tcount, rows;
+    // staged neighbourhood of every tile with particles (saved stage tables,
+    // by slot in the tile order; the tiles with particles come first)
+    std::vector<uint32_t> tcount, rows, order;
     const size_t T = c->b.n_tiles;
     if ((st = d2h(c, tcount, c->b.tile_count, T)) != PBF_OK) return st;
+    if ((st = d2h(c, order, c->b.tile_order, T)) != PBF_OK) return st;
     if ((st = d2h(c, rows, c->b.tile_rows, T * (size_t)kRowWords)) != PBF_OK) return st;
     for (size_t t = 0; t < T; ++t) {
-        if (!tcount[t]) continue;
+        if (!tcount[order[t]]) continue;
         const uint32_t staged = rows[t * (size_t)kRowWords + kBndWords + kStageRows];
         o->max_stage = std::max(o->max_stage, (int32_t)staged);
         if (staged > (uint32_t)kStageCap) o->tiles_unstaged += 1;
@@ -1136,20 +1140,24 @@ pbf_status pbf_debug_neighbours(pbf_ctx *c, int32_t *counts, int32_t *ids, int64
     for (size_t g = 0; g < n; ++g) off[g + 1] = off[g] + counts[g];
     *total = off[n];
     if (!ids || cap < off[n] || n == 0) return PBF_OK;
-    // decode the codes with each tile's saved tables (host side)
+    // decode the codes with each tile's saved tables (host side; the tables
+    // are stored by the tile's slot in the tile order)
     const size_t T = c->b.n_tiles, stride = (size_t)c->b.nbr_stride;
-    std::vector<uint32_t> tstart, tcount, rows;
+    std::vector<uint32_t> tstart, tcount, rows, order;
     std::vector<uint16_t> codes;
     if ((st = d2h(c, tstart, c->b.tile_start, T + 1)) != PBF_OK) return st;
     if ((st = d2h(c, tcount, c->b.tile_count, T)) != PBF_OK) return st;
+    if ((st = d2h(c, order, c->b.tile_order, T)) != PBF_OK) return st;
     if ((st = d2h(c, rows, c->b.tile_rows, T * (size_t)kRowWords)) != PBF_OK) return st;
     if ((st = d2h(c, codes, (const uint16_t *)c->b.nbr, n * stride)) != PBF_OK) return st;
     // group g of particle p holds codes 8g..8g+7 at u16 offset 8 (g n + p)
     auto code_at = [&](size_t p, int32_t q) -> uint32_t {
         return codes[8 * ((size_t)(q / 8) * n + p) + (size_t)(q % 8)];
     };
-    for (size_t t = 0; t < T; ++t) {
-        const uint32_t *bnd = rows.data() + t * (size_t)kRowWords;  // [row][x], then LDS bases
+    for (size_t sl = 0; sl < T; ++sl) {
+        const uint32_t t = order[sl];
+        if (!tcount[t]) continue;  // no tables saved
+        const uint32_t *bnd = rows.data() + sl * (size_t)kRowWords;  // [row][x], then LDS bases
         const uint32_t *base = bnd + kBndWords;
         const bool fits = base[kStageRows] <= (uint32_t)kStageCap;
         for (uint32_t pl = 0; pl < tcount[t]; ++pl) {
@@ -1222,6 +1230,7 @@ pbf_status pbf_density(pbf_ctx *c, double *out, float *rho_rel, int32_t on_devic
         al(&nd.pmeta, (size_t)n);
         al(&nd.pslot, (size_t)n);
         al(&nd.tile_rows, T * kRowWords);
+        al(&nd.tile_rec, T);
         al(&nd.tile_order, T);
         al(&nd.tile_start, T + 1);
         al(&nd.tile_count, T);
@@ -1434,11 +1443,12 @@ pbf_status pbf_rollout_backward(pbf_ctx *c, const float *dl_dx, const float *dl_
             r.pmeta = (uint32_t *)alloc((size_t)n * 4);
             r.pslot = (uint32_t *)alloc((size_t)n * 4);
             r.tile_rows = (uint32_t *)alloc(T_t * kRowWords * 4);
+            r.tile_rec = (uint4 *)alloc(T_t * 16);
             r.tile_order = (uint32_t *)alloc(T_t * 4);
             r.tile_start = (uint32_t *)alloc((T_t + 1) * 4);
             r.tile_count = (uint32_t *)alloc(T_t * 4);
             r.tile_ge = (uint32_t *)alloc((PBF_MAX_ITERS + 2) * 4);
-            ok = r.id && r.lvl && r.nbr && r.pmeta && r.pslot && r.tile_rows && r.tile_order &&
+            ok = r.id && r.lvl && r.nbr && r.pmeta && r.pslot && r.tile_rows && r.tile_rec && r.tile_order &&
                  r.tile_start && r.tile_count && r.tile_ge;
             for (int k = 0; k <= K && ok; ++k) ok = (r.snap[k] = (float4 *)alloc((size_t)n * 16)) != nullptr;
         }

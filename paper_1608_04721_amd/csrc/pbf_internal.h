@@ -15,7 +15,9 @@ constexpr int kTileEdge = 4;
 constexpr int kStageEdge = kTileEdge + 2;
 constexpr int kStageRows = kStageEdge * kStageEdge;
 constexpr int kOwnRows = kTileEdge * kTileEdge;
-constexpr int kStageCap = 2304;    // float4 entries staged in LDS (36 KiB)
+// float4 entries staged in LDS: a third above the rest occupancy of eight
+// particles per cell (2304 entries, 36 KiB, for 6^3 cells), in whole waves
+constexpr int kStageCap = kStageEdge * kStageEdge * kStageEdge * 32 / 3 / 64 * 64;
 constexpr int kTileThreads = 512;  // threads of a solver-pass tile workgroup (at most)
 constexpr int kNbrThreads = 512;   // threads of a neighbour-build tile workgroup (at most)
 constexpr int kDecodeThreads = 256;  // threads of a workgroup decoding a tile's codes (reverse pass)
@@ -23,6 +25,7 @@ constexpr int kBndWords = kStageRows * (kStageEdge + 1);  // cell bounds of the 
 constexpr int kRowWords = kBndWords + kStageRows + 1;     // saved tables per tile
 constexpr uint32_t kXcds = 8;       // accelerator complex dies of an MI355X (own L2 each)
 constexpr int kSegOffBits = 10;    // fallback neighbour code: row << 10 | offset
+static_assert(kStageRows <= 64 && kOwnRows <= 64, "staged row in six bits, an own row per lane");
 // LDS stage entry kStageCap (one past the staged particles) holds a point
 // this far away; its code pads the last group of a neighbour list
 constexpr uint32_t kFarCode = kStageCap;
@@ -184,7 +187,10 @@ struct StepBuffers {
     uint32_t *level_counts;  // (n_iters + 1) * n_level_blocks, scanned in place
     uint32_t *tile_ge;       // [PBF_MAX_ITERS + 2]: tiles with level >= L
     uint32_t *tile_order;    // tiles by descending level, ties by tile index
-    uint32_t *tile_rows;     // [n_tiles][kRowWords] stage layout of each tile
+    uint32_t *tile_rows;     // [n_tiles][kRowWords] stage layout of each tile, by its
+                             // slot in tile_order
+    uint4 *tile_rec;         // [n_tiles] by slot in tile_order: tile, first p, own
+                             // particles, scene (written by the neighbour build)
     // per particle, p order
     uint4 *nbr;              // [nbr_stride / 8][n] groups of eight u16 neighbour codes
     uint32_t *pmeta;         // neighbour count, level, own stage index (see make_meta)
@@ -213,6 +219,7 @@ struct StepRecord {
     uint4 *nbr;
     uint32_t *pmeta, *pslot;
     uint32_t *tile_rows, *tile_order, *tile_start, *tile_count, *tile_ge;
+    uint4 *tile_rec;
     float4 *snap[PBF_MAX_ITERS_INTERNAL + 1];  // (z^k, lambda^k) for k < K; snap[K] = z^K
 };
 
@@ -254,6 +261,7 @@ struct DensityBuffers {
     uint4 *nbr;
     uint32_t *pmeta, *pslot;
     uint32_t *tile_rows, *tile_order, *tile_start, *tile_count, *tile_ge;
+    uint4 *tile_rec;
     uint8_t *tile_lvl;
     uint32_t *err;
     unsigned long long *totals;

@@ -883,16 +883,19 @@ __global__ void k_tile_prepare(uint32_t n_tiles, const SceneDev *__restrict__ sc
         b = row_bound(t, cell_start, sy, sz, kTileEdge + 1);
     }
     const uint32_t count = wave_sum(b - a);
-    // four lanes per own row, each taking every fourth particle of it, with
-    // eight loads issued together (longer rows take another round)
-    static_assert(kOwnRows * 4 == 64, "four lanes per own row");
-    const int o = lane >> 2;
-    const uint32_t ao = __shfl(a, o, 64), bo = __shfl(b, o, 64);
+    // kPrepLanes lanes per own row, each taking every kPrepLanes-th particle
+    // of it, with eight loads issued together (longer rows take another round)
+    constexpr int kPrepLanes = 64 / kOwnRows;
+    static_assert(kPrepLanes >= 1, "an own row per lane at least");
+    const int o = min(lane / kPrepLanes, kOwnRows - 1);
+    const uint32_t ao = __shfl(a, o, 64), bsh = __shfl(b, o, 64);
+    const uint32_t bo = lane < kOwnRows * kPrepLanes ? bsh : ao;
     uint32_t mx = 0;
-    for (uint32_t e0 = ao + (uint32_t)(lane & 3); e0 < bo; e0 += 32) {
+    for (uint32_t e0 = ao + (uint32_t)(lane % kPrepLanes); e0 < bo; e0 += 8 * kPrepLanes) {
         uint32_t v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = e0 + 4 * q < bo ? (uint32_t)lvl[e0 + 4 * q] : 0u;
+        for (int q = 0; q < 8; ++q)
+            v[q] = e0 + kPrepLanes * q < bo ? (uint32_t)lvl[e0 + kPrepLanes * q] : 0u;
 #pragma unroll
         for (int q = 0; q < 8; ++q) mx = max(mx, v[q]);
     }
@@ -1309,7 +1312,7 @@ __global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(8))
     const float4 *__restrict__ xs, const uint8_t *__restrict__ lvl, int64_t n, int cap,
     uint4 *__restrict__ nbr, uint32_t *__restrict__ pmeta, uint32_t *__restrict__ pslot,
     const uint32_t *__restrict__ tile_count, uint32_t *__restrict__ rows,
-    uint32_t *__restrict__ err, uint32_t tx)
+    uint32_t *__restrict__ err, uint32_t tx, uint4 *__restrict__ tile_rec)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
@@ -1321,10 +1324,15 @@ __global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(8))
     const TileLoc t = tile_locate(tile, tile_scene, sc);
     const bool fits = tile_tables(t, cell_start, tb);
     if (!SPLIT) last = tb.own[kOwnRows];
-    // keep the tables for the solver passes of this step
-    if (first == 0)
+    // keep the tables and the tile's record for the solver passes of this
+    // step, at the tile's slot in tile_order (their first loads)
+    if (first == 0) {
         for (int e = threadIdx.x; e < kRowWords; e += blockDim.x)
-            rows[(size_t)tile * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
+            rows[(size_t)slot * kRowWords + e] = e < kBndWords ? (&tb.bnd[0][0])[e] : tb.base[e - kBndWords];
+        if (threadIdx.x == 0)
+            tile_rec[slot] = make_uint4(tile, tile_start[tile], SPLIT ? tile_count[tile] : tb.own[kOwnRows],
+                                        tile_scene[tile]);
+    }
     const float h2 = t.S->h2;
     const uint32_t p0 = tile_start[tile];
     // positions of the own particles in the part (uniform condition); the
@@ -1355,12 +1363,12 @@ __global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(8))
 // Tables of a tile saved by k_neighbours (cell bounds of the staged rows and
 // their LDS offsets): load them and stage `src` (all threads; ends with a
 // barrier); returns whether the stage fits in LDS.
-__device__ __forceinline__ bool stage_rows(const uint32_t *__restrict__ rows, uint32_t tile,
+__device__ __forceinline__ bool stage_rows(const uint32_t *__restrict__ rows, uint32_t slot,
                                            const float4 *__restrict__ src, TileTables &tb,
                                            float4 *__restrict__ stage)
 {
     for (int e = threadIdx.x; e < kRowWords; e += blockDim.x) {
-        const uint32_t w = rows[(size_t)tile * kRowWords + e];
+        const uint32_t w = rows[(size_t)slot * kRowWords + e];
         if (e < kBndWords) (&tb.bnd[0][0])[e] = w;
         else tb.base[e - kBndWords] = w;
     }
@@ -1503,24 +1511,22 @@ __device__ __forceinline__ void tile_lambda(int k, const SceneDev &S, const Tile
 // read only xyz of the same buffer.
 template <bool SPLIT>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_lambda(
-    int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
-    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
-    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
-    const uint32_t *__restrict__ rows, float4 *__restrict__ xs, int64_t n,
-    const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
+    int k, const SceneDev *__restrict__ sc, const uint4 *__restrict__ tile_rec,
+    const uint32_t *__restrict__ tile_ge, const uint32_t *__restrict__ rows, float4 *__restrict__ xs,
+    int64_t n, const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
     const uint32_t *__restrict__ pslot, uint32_t tx)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;
     if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[k + 1], slot)) return;  // active tiles
-    const uint32_t tile = tile_order[slot];
-    const SceneDev &S = sc[tile_scene[tile]];
-    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    const uint4 rec = tile_rec[slot];  // tile, first p, own particles, scene
+    const SceneDev &S = sc[rec.w];
+    const uint32_t p0 = rec.y, nown = rec.z;
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
-    if (!stage_rows(rows, tile, xs, tb, stage))
+    if (!stage_rows(rows, slot, xs, tb, stage))
         tile_lambda<false, !SPLIT, false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
     else if (S.h <= 1.f)
         tile_lambda<true, !SPLIT, true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
@@ -1586,25 +1592,23 @@ __device__ __forceinline__ void tile_update(int k, const SceneDev &S, const Tile
 // from now on.
 template <bool SPLIT, bool CONTACTS>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_update(
-    int k, const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
-    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
-    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
-    const uint32_t *__restrict__ rows, const float4 *__restrict__ xs_in,
-    float4 *__restrict__ xs_out, int64_t n, const uint4 *__restrict__ nbr,
-    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot,
-    const uint8_t *__restrict__ contact, uint32_t tx)
+    int k, const SceneDev *__restrict__ sc, const uint4 *__restrict__ tile_rec,
+    const uint32_t *__restrict__ tile_ge, const uint32_t *__restrict__ rows,
+    const float4 *__restrict__ xs_in, float4 *__restrict__ xs_out, int64_t n,
+    const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
+    const uint32_t *__restrict__ pslot, const uint8_t *__restrict__ contact, uint32_t tx)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;  // tiles with a particle of level >= k
     if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[k > 1 ? k : 1], slot)) return;
-    const uint32_t tile = tile_order[slot];
-    const SceneDev &S = sc[tile_scene[tile]];
-    const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
+    const uint4 rec = tile_rec[slot];  // tile, first p, own particles, scene
+    const SceneDev &S = sc[rec.w];
+    const uint32_t p0 = rec.y, nown = rec.z;
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
-    if (!stage_rows(rows, tile, xs_in, tb, stage))
+    if (!stage_rows(rows, slot, xs_in, tb, stage))
         tile_update<false, CONTACTS, false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact,
                                             p0, nown, first, last, hd);
     else if (S.h <= 1.f)
@@ -1677,13 +1681,11 @@ __device__ __forceinline__ void tile_density(const SceneDev &S, const TileTables
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_density(
-    const SceneDev *__restrict__ sc, const uint32_t *__restrict__ tile_scene,
-    const uint32_t *__restrict__ tile_order, const uint32_t *__restrict__ tile_ge,
-    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_count,
-    const uint32_t *__restrict__ rows, const float4 *__restrict__ x, int64_t n,
-    const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
-    const uint32_t *__restrict__ pslot, float *__restrict__ rho, double *__restrict__ part_sum,
-    float *__restrict__ part_max)
+    const SceneDev *__restrict__ sc, const uint4 *__restrict__ tile_rec,
+    const uint32_t *__restrict__ tile_ge, const uint32_t *__restrict__ rows,
+    const float4 *__restrict__ x, int64_t n, const uint4 *__restrict__ nbr,
+    const uint32_t *__restrict__ pmeta, const uint32_t *__restrict__ pslot,
+    float *__restrict__ rho, double *__restrict__ part_sum, float *__restrict__ part_max)
 {
     __shared__ TileTables tb;
     __shared__ float4 stage[kStageEntries];
@@ -1693,10 +1695,10 @@ __global__ __launch_bounds__(kTileThreads) void k_density(
     float mx = 0.f;
     uint32_t slot;
     if (xcd_slot(blockIdx.x, tile_ge[1], slot)) {  // uniform per workgroup
-        const uint32_t tile = tile_order[slot];
-        const SceneDev &S = sc[tile_scene[tile]];
-        const uint32_t p0 = tile_start[tile], nown = tile_count[tile];
-        if (stage_rows(rows, tile, x, tb, stage))
+        const uint4 rec = tile_rec[slot];  // tile, first p, own particles, scene
+        const SceneDev &S = sc[rec.w];
+        const uint32_t p0 = rec.y, nown = rec.z;
+        if (stage_rows(rows, slot, x, tb, stage))
             tile_density<true>(S, tb, stage, x, n, nbr, pmeta, pslot, p0, nown, rho, sum, mx);
         else
             tile_density<false>(S, tb, stage, x, n, nbr, pmeta, pslot, p0, nown, rho, sum, mx);
@@ -1839,6 +1841,7 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
         b.pmeta = rec->pmeta;
         b.pslot = rec->pslot;
         b.tile_rows = rec->tile_rows;
+        b.tile_rec = rec->tile_rec;
         b.tile_order = rec->tile_order;
         b.tile_start = rec->tile_start;
         b.tile_count = rec->tile_count;
@@ -1903,21 +1906,19 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
                                   : (ct ? k_update<false, true> : k_update<false, false>);
     LAUNCH(K_NEIGHBOURS, TX * SPLIT, bs[K_NEIGHBOURS], nbr_kernel, b.scenes, b.tile_scene,
            b.tile_order, b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap,
-           b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX);
+           b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX, b.tile_rec);
     if (ct)
         LAUNCH(K_CONTACTS, blocks_for(n, bs[K_CONTACTS]), bs[K_CONTACTS], k_contacts, n, b.scenes,
                b.x[nxt], b.xs[0], b.lvl[nxt], b.contact);
     for (int k = 0; k < K; ++k) {
         float4 *xin = b.xs[k & 1], *xout = b.xs[(k + 1) & 1];
-        LAUNCH(K_LAMBDA, TX * SPLIT, bs[K_LAMBDA], lam_kernel, k, b.scenes, b.tile_scene,
-               b.tile_order, b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, n, b.nbr,
-               b.pmeta, b.pslot, TX);
+        LAUNCH(K_LAMBDA, TX * SPLIT, bs[K_LAMBDA], lam_kernel, k, b.scenes, b.tile_rec, b.tile_ge,
+               b.tile_rows, xin, n, b.nbr, b.pmeta, b.pslot, TX);
         if (rec && (e = hipMemcpyAsync(rec->snap[k], xin, sizeof(float4) * n,
                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;
-        LAUNCH(K_UPDATE, TX * SPLIT, bs[K_UPDATE], upd_kernel, k, b.scenes, b.tile_scene,
-               b.tile_order, b.tile_ge, b.tile_start, b.tile_count, b.tile_rows, xin, xout, n,
-               b.nbr, b.pmeta, b.pslot, b.contact, TX);
+        LAUNCH(K_UPDATE, TX * SPLIT, bs[K_UPDATE], upd_kernel, k, b.scenes, b.tile_rec, b.tile_ge,
+               b.tile_rows, xin, xout, n, b.nbr, b.pmeta, b.pslot, b.contact, TX);
     }
     if (rec) {
         if ((e = hipMemcpyAsync(rec->snap[K], b.xs[K & 1], sizeof(float4) * n,
@@ -1943,6 +1944,7 @@ hipError_t enqueue_density(const StepBuffers &b0, int cur, const LaunchShape &ls
     b.pmeta = d.pmeta;
     b.pslot = d.pslot;
     b.tile_rows = d.tile_rows;
+    b.tile_rec = d.tile_rec;
     b.tile_order = d.tile_order;
     b.tile_start = d.tile_start;
     b.tile_count = d.tile_count;
@@ -1987,10 +1989,9 @@ hipError_t enqueue_density(const StepBuffers &b0, int cur, const LaunchShape &ls
     }
     LAUNCH(K_NEIGHBOURS, TX, bs[K_NEIGHBOURS], k_neighbours<false>, b.scenes, b.tile_scene,
            b.tile_order, b.tile_ge, b.tile_start, b.cell_start, d.xs, b.lvl[nxt], n, b.nbr_cap,
-           b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX);
-    LAUNCH(K_LAMBDA, TX, kTileThreads, k_density, b.scenes, b.tile_scene, b.tile_order, b.tile_ge,
-           b.tile_start, b.tile_count, b.tile_rows, d.xs, n, b.nbr, b.pmeta, b.pslot, d.rho_slot,
-           d.part_sum, d.part_max);
+           b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX, b.tile_rec);
+    LAUNCH(K_LAMBDA, TX, kTileThreads, k_density, b.scenes, b.tile_rec, b.tile_ge, b.tile_rows,
+           d.xs, n, b.nbr, b.pmeta, b.pslot, d.rho_slot, d.part_sum, d.part_max);
     LAUNCH(K_COMMIT, 1, 1024, k_density_finish, TX, n, d.part_sum, d.part_max, d.out);
     if (rho_id)
         LAUNCH(K_COMMIT, blocks_for(n, 256), 256, k_unpermute_scalar, n, d.rho_slot, b.id[nxt],
