@@ -1235,16 +1235,21 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         // each code is stored as it is found, 16 bits at a time; the pointer
         // steps one code inside a group and on to the particle's next group
         // (n groups further) after the eighth code
-        uint16_t *__restrict__ w = reinterpret_cast<uint16_t *>(nbr + p);
-        const int64_t jump = 8 * n - 7;
-        auto put = [&](uint32_t code) {
-            if (cnt < cap8) *w = (uint16_t)code;
+        char *__restrict__ out = reinterpret_cast<char *>(nbr + p);
+        const uint32_t jump = (uint32_t)(16 * n - 14);  // bytes from the last code of a group
+        auto store = [&](uint32_t code) {  // no capacity test
+            *reinterpret_cast<uint16_t *>(out) = (uint16_t)code;
             ++cnt;
-            w += (cnt & 7u) ? (int64_t)1 : jump;
+            out += (cnt & 7u) ? 2u : jump;
+        };
+        auto put = [&](uint32_t code) {
+            if (cnt < cap8) *reinterpret_cast<uint16_t *>(out) = (uint16_t)code;
+            ++cnt;
+            out += (cnt & 7u) ? 2u : jump;
         };
 #pragma unroll 1
-        for (int w = 0; w < 9; ++w) {
-            const int r2 = (sz + w / 3 - 1) * kStageEdge + (sy + w % 3 - 1);
+        for (int win = 0; win < 9; ++win) {
+            const int r2 = (sz + win / 3 - 1) * kStageEdge + (sy + win % 3 - 1);
             const uint32_t g0 = tb.bnd[r2][0];
             const uint32_t ja = tb.bnd[r2][lx - 1], len = tb.bnd[r2][lx + 2] - ja;
             const uint32_t l0 = tb.base[r2] + (ja - g0);
@@ -1276,7 +1281,15 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                 m = __builtin_bitreverse32(m) >> (32u - tested);
                 if (cl < 32u) m &= (1u << cl) - 1u;
                 if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1u << (i - ja - c0));  // not itself
-                // ... then its hits become codes, in candidate order
+                // ... then its hits become codes, in candidate order (without
+                // a capacity test per code while the chunk's hits have room)
+                if (FITS && cnt + (uint32_t)__popc(m) <= cap8) {
+                    const uint32_t lc = l0 + c0;
+                    while (m) {
+                        store(lc + (uint32_t)(__ffs(m) - 1));
+                        m &= m - 1u;
+                    }
+                }
                 while (m) {
                     const uint32_t c = c0 + (uint32_t)(__ffs(m) - 1);
                     m &= m - 1u;
