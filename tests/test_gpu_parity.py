@@ -311,6 +311,31 @@ def test_launch_shapes_do_not_change_results(name):
             assert np.array_equal(sim.positions(), x_ref), shape
 
 
+def test_rank_order_inside_tiles_does_not_change_results():
+    """The neighbour build places each tile's particles by descending level
+    (ranks given in rounds of one workgroup's threads, at most four rounds;
+    a tile part with more particles keeps cell order).  With 16 particles
+    per cell a tile holds about 1,000 own particles: 512 threads rank them
+    in two rounds, 256 in four, and 128 threads leave them in cell order.
+    Each particle's sums follow its own neighbour list, so all three give
+    the same bits; with levels 1..2 the oracle agrees at the plain bound
+    (this cloud's one-ulp spread over two iterations is 4e-6 .. 8e-6)."""
+    sc = scenes.random_cloud(16000, seed=41, extent=1.0, n_min=1, n_max=2, dup_frac=0.0)
+    out = []
+    for t in (512, 256, 128):
+        with _sim(sc, max_neighbours=1000) as sim:
+            sim.set_block_size("neighbours", t)
+            sim.step(2)
+            out.append((sim.positions(), sim.debug_lambda()))
+    for x, lam in out[1:]:
+        assert np.array_equal(x, out[0][0]) and np.array_equal(lam, out[0][1])
+    with _sim(sc, max_neighbours=1000) as sim:
+        sim.set_block_size("neighbours", 128)
+        sim.step(1)
+        x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
+        _check_step(sc, sim, x_ref, v_ref, info)
+
+
 def test_resume_from_saved_state_bit_identical():
     sc = scenes.block(12, 12, 12, seed=13, n_min=2, n_max=6, levels="random", vel_sigma=0.3)
     with _sim(sc) as a:
