@@ -111,6 +111,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_double)]
         L.orc_levels.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod), ctypes.c_void_p,
                                  ctypes.c_void_p]
+        L.orc_levels_guarded.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Lod), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         L.orc_cell_keys.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
         L.orc_counting_sort.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
@@ -227,15 +229,20 @@ def contact_found(kind, centre, a, x, margin) -> bool:
     return bool(lib().orc_contact_found(ctypes.byref(o), _ptr(x, ctypes.c_double), float(margin)))
 
 
-def levels(scene, x) -> np.ndarray:
+def levels(scene, x, guard: bool = False):
+    """Levels N_i (Eq. 8) at positions x, in FP64.  guard=True also returns a
+    bool array marking the particles within the guard band of a bin edge,
+    where a lower-precision evaluation may give the neighbouring level."""
     p = params(scene)
     hold = _LodHolder(scene)
     x = np.ascontiguousarray(x, np.float64)
     out = np.zeros(scene.n, np.int32)
-    rc = lib().orc_levels(ctypes.byref(p), ctypes.byref(hold.lod), x.ctypes.data, out.ctypes.data)
+    near = np.zeros(max(scene.n, 1), np.uint8)
+    rc = lib().orc_levels_guarded(ctypes.byref(p), ctypes.byref(hold.lod), x.ctypes.data,
+                                  out.ctypes.data, near.ctypes.data)
     if rc != ORC_OK:
         raise ValueError(f"orc_levels failed ({rc})")
-    return out
+    return (out, near[:scene.n].astype(bool)) if guard else out
 
 
 def apbf_step(scene, x, v, trace=False, mode=None, levels=None, n_min=None, n_max=None):

@@ -46,10 +46,11 @@
  *     clamped into the grid; ties in the counting sort keep particle-ID
  *     order (a stable counting sort of the particles listed by ID).
  *   - Distance-to-camera levels: t = clamp((d - d_near)/(d_far - d_near)),
- *     N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max), decided
- *     in float32 like the kernel (an integer chosen by floating point is
- *     chosen in the same precision on both sides); everything else is FP64.
- *     A t that is not a number (a range of zero width) counts as 0.  Several
+ *     N = clamp(n_max - floor(t (n_max - n_min + 1)), n_min, n_max), in
+ *     FP64; a particle whose t (n_max - n_min + 1) lies within
+ *     ORC_LEVEL_GUARD of an interior bin edge is reported as near the edge,
+ *     where an evaluation in lower precision may take the neighbouring
+ *     level.  A t that is not a number (a range of zero width) counts as 0.  Several
  *     cameras blend by taking the highest level; an automatic range is the
  *     min/max of the distances over the particles at the step's start
  *     (Section 4.1).
@@ -459,16 +460,30 @@ static void contact_response(const orc_params *p, const orc_contacts *oc, uint32
 /* ------------------------------------------------------------------ */
 
 /* Level from a distance (DTC and DTVS, Section 4.1): linear map of the
- * distance range [d_near, d_far] onto the levels n_max .. n_min, decided in
- * float32 like the kernel. */
-static int32_t level_of_distance(const orc_params *p, float d, float d_near, float d_far)
+ * distance range [d_near, d_far] onto the levels n_max .. n_min, in FP64.
+ * With u = t (n_max - n_min + 1), the level changes at the integers
+ * 1 .. n_max - n_min; *near_edge (if given) is set when u lies within
+ * ORC_LEVEL_GUARD of one of them.  (A float32 evaluation of u from the same
+ * inputs errs by a few units in the last place, below 1e-5 for u <= 32.) */
+#define ORC_LEVEL_GUARD 2e-5
+static int32_t level_of_distance(const orc_params *p, double d, double d_near, double d_far,
+                                 uint8_t *near_edge)
 {
-    float t = (d - d_near) / (d_far - d_near);
-    if (!(t >= 0.0f)) t = 0.0f;  /* negative, or not a number */
-    if (t > 1.0f) t = 1.0f;
-    int32_t L = p->n_max - (int32_t)floorf(t * (float)(p->n_max - p->n_min + 1));
+    double t = (d - d_near) / (d_far - d_near);
+    if (!(t >= 0.0)) t = 0.0;  /* negative, or not a number */
+    if (t > 1.0) t = 1.0;
+    const int32_t nb = p->n_max - p->n_min + 1;
+    const double u = t * (double)nb;
+    const double f = floor(u);
+    int32_t L = p->n_max - (int32_t)f;
     if (L < p->n_min) L = p->n_min;
     if (L > p->n_max) L = p->n_max;
+    if (near_edge) {
+        const double below = u - f, above = f + 1.0 - u;  /* to the edges f and f + 1 */
+        if ((below < ORC_LEVEL_GUARD && f >= 1.0 && f <= (double)(nb - 1)) ||
+            (above < ORC_LEVEL_GUARD && f + 1.0 <= (double)(nb - 1)))
+            *near_edge = 1;
+    }
     return L;
 }
 
@@ -528,7 +543,8 @@ static int dtvs_project(const orc_lod *lod, const double *xi, orc_proj *o)
  * particle's distance to the visible surface is its own distance minus the
  * depth at its pixel.  Particles behind the camera or outside the image get
  * the largest distance (lowest level). */
-static int levels_dtvs(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+static int levels_dtvs(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev,
+                       uint8_t *near_edge)
 {
     const int32_t W = lod->width, H = lod->height;
     if (W < 1 || H < 1) return ORC_ERR_ARG;
@@ -560,45 +576,42 @@ static int levels_dtvs(const orc_params *p, const orc_lod *lod, const double *x,
         dist[i] = d;
     }
     if (df < dn) dn = df = 0.0f;  /* automatic range with no particle seen */
-    for (int32_t i = 0; i < p->n; ++i) lev[i] = level_of_distance(p, dist[i], dn, df);
+    for (int32_t i = 0; i < p->n; ++i)
+        lev[i] = level_of_distance(p, dist[i], dn, df, near_edge ? near_edge + i : NULL);
     free(dist);
     free(depth);
     return ORC_OK;
 }
 
-/* Distance of a particle to a camera, float32 with a fixed order. */
-static float camera_distance(const double *xi, const double *cam)
+/* Distance of a particle to a camera. */
+static double camera_distance(const double *xi, const double *cam)
 {
-    float dx = (float)xi[0] - (float)cam[0];
-    float dy = (float)xi[1] - (float)cam[1];
-    float dz = (float)xi[2] - (float)cam[2];
-    float d2 = dx * dx;
-    d2 = d2 + dy * dy;
-    d2 = d2 + dz * dz;
-    return sqrtf(d2);
+    const double dx = xi[0] - cam[0], dy = xi[1] - cam[1], dz = xi[2] - cam[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
 /* Distance-to-camera levels over 1 + n_extra cameras: each camera maps its
  * distance through its range (given, or the min/max over the particles);
  * the particle takes the highest of the levels. */
-static int levels_dtc(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+static int levels_dtc(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev,
+                      uint8_t *near_edge)
 {
     const int nc = 1 + lod->n_extra;
     if (lod->n_extra < 0 || lod->n_extra > 3) return ORC_ERR_ARG;
     const double *cam[4] = {lod->camera, lod->extra_camera[0], lod->extra_camera[1], lod->extra_camera[2]};
-    float dn[4], df[4];
-    dn[0] = (float)lod->d_near;
-    df[0] = (float)lod->d_far;
+    double dn[4], df[4];
+    dn[0] = lod->d_near;
+    df[0] = lod->d_far;
     for (int c = 1; c < nc; ++c) {
-        dn[c] = (float)lod->extra_range[c - 1][0];
-        df[c] = (float)lod->extra_range[c - 1][1];
+        dn[c] = lod->extra_range[c - 1][0];
+        df[c] = lod->extra_range[c - 1][1];
     }
     if (lod->auto_range)
         for (int c = 0; c < nc; ++c) {
-            dn[c] = FLT_MAX;
-            df[c] = 0.0f;
+            dn[c] = DBL_MAX;
+            df[c] = 0.0;
             for (int32_t i = 0; i < p->n; ++i) {
-                const float d = camera_distance(x + 3 * (int64_t)i, cam[c]);
+                const double d = camera_distance(x + 3 * (int64_t)i, cam[c]);
                 if (d < dn[c]) dn[c] = d;
                 if (d > df[c]) df[c] = d;
             }
@@ -606,7 +619,8 @@ static int levels_dtc(const orc_params *p, const orc_lod *lod, const double *x, 
     for (int32_t i = 0; i < p->n; ++i) {
         int32_t L = 0;
         for (int c = 0; c < nc; ++c) {
-            const int32_t Lc = level_of_distance(p, camera_distance(x + 3 * (int64_t)i, cam[c]), dn[c], df[c]);
+            const int32_t Lc = level_of_distance(p, camera_distance(x + 3 * (int64_t)i, cam[c]), dn[c], df[c],
+                                                 near_edge ? near_edge + i : NULL);
             if (Lc > L) L = Lc;
         }
         lev[i] = L;
@@ -614,21 +628,20 @@ static int levels_dtc(const orc_params *p, const orc_lod *lod, const double *x, 
     return ORC_OK;
 }
 
-int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+int orc_levels_guarded(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev,
+                       uint8_t *near_edge)
 {
+    if (near_edge)
+        for (int32_t i = 0; i < p->n; ++i) near_edge[i] = 0;
     if (lod->mode == 3) {
-        int rc = levels_dtvs(p, lod, x, lev);
+        int rc = levels_dtvs(p, lod, x, lev, near_edge);
         if (rc) return rc;
         for (int32_t i = 0; i < p->n; ++i)
             if (lev[i] < 1 || lev[i] < p->n_min || lev[i] > p->n_max) return ORC_ERR_ARG;
         return ORC_OK;
     }
     if (lod->mode == 2) {
-        /* The level is an integer decided by floating point, so it is
-         * decided in the kernel's precision: float32, one rounding per
-         * operation (no contraction), correctly rounded sqrt and division,
-         * in this order. */
-        int rc = levels_dtc(p, lod, x, lev);
+        int rc = levels_dtc(p, lod, x, lev, near_edge);
         if (rc) return rc;
         for (int32_t i = 0; i < p->n; ++i)
             if (lev[i] < 1 || lev[i] < p->n_min || lev[i] > p->n_max) return ORC_ERR_ARG;
@@ -640,6 +653,11 @@ int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t
         lev[i] = L;
     }
     return ORC_OK;
+}
+
+int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t *lev)
+{
+    return orc_levels_guarded(p, lod, x, lev, NULL);
 }
 
 static int check_params(const orc_params *p)

@@ -16,6 +16,8 @@ from __future__ import annotations
 
 import numpy as np
 
+import scenes
+
 
 def extent(sc) -> float:
     return float(np.max(sc.hi.astype(np.float64) - sc.lo.astype(np.float64)))
@@ -117,7 +119,24 @@ def adjoint_spread(sc, steps, cot_fn, trials=2, seed=0):
     return (xT, frozen, rx, rv), worst
 
 
-def ulp_spread_per_particle(sc, x, v, trials=3, seed=0):
+def check_levels(sc, x, lv_gpu):
+    """GPU levels (Eq. 8) against the oracle's FP64 levels at positions x:
+    equal for every particle away from a bin edge; within the oracle's guard
+    band of an edge (where the float32 evaluation may round to the other
+    side) either neighbouring level is accepted.  Returns the number of
+    particles whose levels differ (all of them at an edge)."""
+    import oracle
+
+    ref, near = oracle.levels(sc, np.asarray(x, np.float64), guard=True)
+    lv = np.asarray(lv_gpu).astype(np.int64)
+    diff = lv != ref
+    away = diff & ~near
+    assert not away.any(), f"levels differ away from bin edges at {np.flatnonzero(away)[:10]}"
+    assert np.all(np.abs(lv - ref)[diff] <= 1)
+    return int(diff.sum())
+
+
+def ulp_spread_per_particle(sc, x, v, trials=3, seed=0, levels=None):
     """Per-particle conditioning of one oracle step from the state (x, v):
     the largest change of each particle's position and final lambda over
     `trials` runs in which every input coordinate moves by one float32 ulp
@@ -131,8 +150,11 @@ def ulp_spread_per_particle(sc, x, v, trials=3, seed=0):
     the whole fluid."""
     import oracle
 
+    # with `levels`, every run uses those levels (a one-ulp move must not
+    # carry a particle across a level's bin edge)
+    kw = {} if levels is None else dict(mode=scenes.LOD_EXPLICIT, levels=levels)
     x32 = np.asarray(x, np.float32)
-    x1, v1, i1 = oracle.apbf_step(sc, x32, v, trace=True)
+    x1, v1, i1 = oracle.apbf_step(sc, x32, v, trace=True, **kw)
     lv = i1["levels"]
     n = x32.shape[0]
     lam1 = i1["lambda_iter"][lv - 1, np.arange(n)]
@@ -142,7 +164,7 @@ def ulp_spread_per_particle(sc, x, v, trials=3, seed=0):
     for _ in range(trials):
         d = np.where(rng.random(x32.shape) < 0.5, -np.inf, np.inf).astype(np.float32)
         xp = np.nextafter(x32, d).astype(np.float64)
-        x2, _, i2 = oracle.apbf_step(sc, xp, v, trace=True)
+        x2, _, i2 = oracle.apbf_step(sc, xp, v, trace=True, **kw)
         lam2 = i2["lambda_iter"][lv - 1, np.arange(n)]
         dx = np.maximum(dx, np.abs(x2 - x1).max(axis=1))
         dl = np.maximum(dl, np.abs(lam2 - lam1))

@@ -25,7 +25,7 @@ import torch  # noqa: F401  (first import can be slow; keep it out of test timeo
 
 import oracle
 import scenes
-from parity import adjoint_spread, neighbour_mismatch, pos_tol, ref_csr
+from parity import adjoint_spread, check_levels, neighbour_mismatch, pos_tol, ref_csr
 
 pytestmark = pytest.mark.gpu
 
@@ -91,12 +91,14 @@ CASES = {
 def test_step_adjoint_matches_oracle(case):
     sc = CASES[case]()
     x0, v0 = sc.x0.astype(np.float64), sc.v0.astype(np.float64)
-    x1, v1, info = oracle.apbf_step(sc, x0, v0, trace=True)
-    frozen = [(info["levels"], info["nbr_off"], info["nbr_ids"])]
     sim = _sim(sc)
     sim.rollout_forward(1, 1)
-    # same structure on both sides
-    assert np.array_equal(sim.debug_levels().astype(np.int32), info["levels"])
+    # same structure on both sides: the GPU's levels (checked against the
+    # oracle's FP64 levels, either level at a bin edge) for both
+    lv = sim.debug_levels().astype(np.int32)
+    check_levels(sc, x0, lv)
+    x1, v1, info = oracle.apbf_step(sc, x0, v0, trace=True, mode=scenes.LOD_EXPLICIT, levels=lv)
+    frozen = [(info["levels"], info["nbr_off"], info["nbr_ids"])]
     assert neighbour_mismatch(sc, sim.debug_neighbours(), ref_csr(info), info["xs_iter"][0]) == 0
     assert np.abs(sim.positions() - x1).max() <= pos_tol(sc)
     a, b = _cotangents(sc.n, 1)

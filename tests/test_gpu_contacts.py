@@ -18,7 +18,7 @@ import torch  # noqa: F401  (first import can be slow; keep it out of test timeo
 
 import oracle
 import scenes
-from parity import pos_tol
+from parity import check_levels, pos_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +64,13 @@ def _near_bound(sc, xs):
 
 
 def _compare_step(sc, sim, x, v, tol=None):
-    """One GPU step against one oracle step from the same float32 state."""
-    x_ref, v_ref, info = oracle.apbf_step(sc, x.astype(np.float64), v.astype(np.float64), trace=True)
+    """One GPU step against one oracle step from the same float32 state (the
+    oracle takes the GPU's levels once they are checked against its own)."""
     sim.step(1)
+    lv = sim.debug_levels().astype(np.int32)
+    check_levels(sc, x, lv)
+    x_ref, v_ref, info = oracle.apbf_step(sc, x.astype(np.float64), v.astype(np.float64), trace=True,
+                                          mode=scenes.LOD_EXPLICIT, levels=lv)
     xg = sim.positions().astype(np.float64)
     vg = sim.velocities().astype(np.float64)
     tol = pos_tol(sc) if tol is None else tol

@@ -1,9 +1,12 @@
 """GPU parity of the distance-to-the-visible-surface levels (Section 4.1).
 
-The levels are integers decided by float32 arithmetic in a fixed order on
-both sides (projection, splat radius, distance, depth minimum, linear map),
-so they must match the oracle bit for bit; the step that uses them is then
-checked like any other step.
+The depth image is a rasterisation whose pixels, splat radii and minima
+are decided in float32 in a fixed order on both sides (projection, splat
+radius, distance, depth minimum); the linear map of the resulting distance
+onto the levels is FP64 in the oracle, so the levels must match it except
+for particles within its guard band of a bin edge, where either level is
+accepted.  The step that uses them is then checked like any other step,
+with the oracle taking the GPU's levels.
 """
 import numpy as np
 import pytest
@@ -11,7 +14,7 @@ import torch  # noqa: F401  (first import can be slow; keep it out of test timeo
 
 import oracle
 import scenes
-from parity import pos_tol
+from parity import check_levels, pos_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -43,28 +46,28 @@ def test_levels_match_oracle_and_step():
     sc = _side_view(scenes.block(14, 10, 12, seed=5, n_min=2, n_max=7, vel_sigma=0.2))
     lv_ref = oracle.levels(sc, sc.x0.astype(np.float64))
     assert len(set(lv_ref.tolist())) >= 4  # the scene spans the level range
-    x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True)
     with _sim(sc) as sim:
         sim.step(1)
-        assert np.array_equal(sim.debug_levels().astype(np.int32), lv_ref)
+        lv = sim.debug_levels().astype(np.int32)
+        check_levels(sc, sc.x0, lv)
+        x_ref, v_ref, info = oracle.apbf_step(sc, sc.x0, sc.v0, trace=True,
+                                              mode=scenes.LOD_EXPLICIT, levels=lv)
         x = sim.positions().astype(np.float64)
         assert np.abs(x - x_ref).max() <= pos_tol(sc)
         # levels of the next step, from the GPU's own positions
         sim.step(1)
-        lv2 = oracle.levels(sc, x)
-        assert np.array_equal(sim.debug_levels().astype(np.int32), lv2)
+        check_levels(sc, x, sim.debug_levels())
 
 
 def test_full_size_tank_levels():
     tank = scenes.tank_1m()
     sc = scenes.with_dtvs(tank, camera=tank.camera, target=(3.2, 1.6, 3.2), d_far=1.0)
-    lv_ref = oracle.levels(sc, sc.x0.astype(np.float64))
     with _sim(sc) as sim:
         sim.set_graph(True)
         sim.step(1)
         lv = sim.debug_levels().astype(np.int32)
-    assert np.array_equal(lv, lv_ref)
-    print("tank levels", np.bincount(lv_ref, minlength=11)[5:])
+    at_edge = check_levels(sc, sc.x0, lv)
+    print("tank levels", np.bincount(lv, minlength=11)[5:], f"({at_edge} at a bin edge)")
 
 
 def test_wide_splats_and_moving_tank():
@@ -80,7 +83,7 @@ def test_wide_splats_and_moving_tank():
         for _ in range(3):
             x = sim.positions().astype(np.float64)
             sim.step(1)
-            assert np.array_equal(sim.debug_levels().astype(np.int32), oracle.levels(sc, x))
+            check_levels(sc, x, sim.debug_levels())
     # the full tank after some motion: workgroups straddling the end of a
     # cell row take the direct path, the others the LDS tile
     tank = scenes.tank_1m()
@@ -91,7 +94,7 @@ def test_wide_splats_and_moving_tank():
         x = sim.positions().astype(np.float64)
         sim.step(1)
         lv = sim.debug_levels().astype(np.int32)
-    assert np.array_equal(lv, oracle.levels(sc, x))
+    check_levels(sc, x, lv)
 
 
 def test_batch_mixes_level_sources():

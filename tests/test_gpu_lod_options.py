@@ -1,10 +1,13 @@
 """GPU parity of the level options of Section 4.1 (several cameras, automatic
 distance range) and of the unilateral density constraint.
 
-Levels are integers decided in float32 by the same operations on both sides
-(the automatic range is a min/max of those float32 distances, exact in any
-order), so they are compared bit for bit against the oracle evaluated at the
-GPU's own positions; steps are compared like the other parity tests.
+Levels are integers chosen by floating point: the GPU decides them in
+float32, the oracle in FP64 and reports the particles within its guard band
+of a bin edge.  They are compared against the oracle evaluated at the GPU's
+own positions, equal away from the edges and either level at an edge (the
+hand-computed cases sit on exactly representable values and match bit for
+bit); steps are compared like the other parity tests, with the oracle
+taking the GPU's levels.
 """
 import dataclasses
 
@@ -14,7 +17,7 @@ import torch  # noqa: F401  (first import can be slow; keep it out of test timeo
 
 import oracle
 import scenes
-from parity import pos_tol
+from parity import check_levels, pos_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -66,9 +69,11 @@ def test_dtc_options_match_oracle_every_step(case):
         x = sc.x0.astype(np.float64)
         v = sc.v0.astype(np.float64)
         for _ in range(4):
-            x_ref, v_ref, info = oracle.apbf_step(sc, x, v, trace=True)
             sim.step(1)
-            assert np.array_equal(sim.debug_levels().astype(np.int32), info["levels"])
+            lv = sim.debug_levels().astype(np.int32)
+            check_levels(sc, x, lv)
+            x_ref, v_ref, info = oracle.apbf_step(sc, x, v, trace=True, mode=scenes.LOD_EXPLICIT,
+                                                  levels=lv)
             xg, vg = sim.positions(), sim.velocities()
             assert np.abs(xg - x_ref).max() <= pos_tol(sc)
             x, v = xg.astype(np.float64), vg.astype(np.float64)
@@ -86,23 +91,22 @@ def test_dtvs_automatic_range():
     with _sim(sc) as sim:
         for _ in range(3):
             x = sim.positions().astype(np.float64)
-            lv_ref = oracle.levels(sc, x)
             sim.step(1)
-            assert np.array_equal(sim.debug_levels().astype(np.int32), lv_ref)
-    assert len(set(lv_ref.tolist())) >= 4
+            lv = sim.debug_levels().astype(np.int32)
+            check_levels(sc, x, lv)
+    assert len(set(lv.tolist())) >= 4
 
 
 def test_full_size_tank_with_cameras_and_automatic_range():
     tank = scenes.tank_1m()
     sc = dataclasses.replace(tank, auto_range=True,
                              extra_cameras=(((-3.2, 6.4, 3.2), (0.0, 1.0)),))
-    lv_ref = oracle.levels(sc, sc.x0.astype(np.float64))
     with _sim(sc) as sim:
         sim.set_graph(True)
         sim.step(1)
         lv = sim.debug_levels().astype(np.int32)
-    assert np.array_equal(lv, lv_ref)
-    print("tank levels", np.bincount(lv_ref, minlength=11)[5:])
+    at_edge = check_levels(sc, sc.x0, lv)
+    print("tank levels", np.bincount(lv, minlength=11)[5:], f"({at_edge} at a bin edge)")
 
 
 def test_unilateral_steps_match_oracle():

@@ -116,3 +116,31 @@ def test_unilateral_lambda_is_the_compressive_part():
     assert (lb > 0).any() and (lb < 0).any()
     assert np.array_equal(lu, np.minimum(lb, 0.0))
     assert np.all(iu["lambda_iter"] <= 0.0)
+
+
+def test_level_guard_band_marks_the_bin_edges():
+    # levels 1..4 over [0.5, 1.5]: u = 4 (d - 0.5) changes level at d = 0.75,
+    # 1.0 and 1.25 (exact binary values); the clamped ends change nothing
+    xs = [0.5, 0.6, 0.75, 0.9, 1.0, 1.1, 1.25, 1.4, 1.5]
+    sc = _line_scene(xs, camera=(0, 0, 0), d_near=0.5, d_far=1.5)
+    lv, near = oracle.levels(sc, sc.x0.astype(np.float64), guard=True)
+    assert list(lv) == [4, 4, 3, 3, 2, 2, 1, 1, 1]
+    assert list(near) == [False, False, True, False, True, False, True, False, False]
+
+
+def test_float32_levels_differ_only_inside_the_guard_band():
+    # the same map evaluated in float32 (one rounding per operation) on the
+    # 1M tank's initial positions: any particle whose float32 level differs
+    # from the FP64 one lies inside the guard band, and the band is narrow
+    sc = scenes.tank_1m()
+    x = sc.x0[::7].astype(np.float64)
+    sub = dataclasses.replace(sc, x0=sc.x0[::7].copy(), v0=sc.v0[::7].copy())
+    lv, near = oracle.levels(sub, x, guard=True)
+    f = np.float32
+    q = sub.x0 - np.asarray(sc.camera, f)
+    d = np.sqrt(((q[:, 0] * q[:, 0]) + (q[:, 1] * q[:, 1])) + (q[:, 2] * q[:, 2]))
+    t = np.clip((d - f(sc.d_near)) / (f(sc.d_far) - f(sc.d_near)), f(0), f(1))
+    lv32 = np.clip(sc.n_max - np.floor(t * f(sc.n_max - sc.n_min + 1)).astype(np.int64),
+                   sc.n_min, sc.n_max)
+    assert np.all((lv32 == lv) | near)
+    assert near.mean() < 1e-3
