@@ -460,7 +460,7 @@ __global__ void k_lod_predict(int64_t n, const SceneDev *__restrict__ sc,
     if (valid) {
         const float4 xi = x[s];
         const SceneDev &S = sc[__float_as_int(xi.w)];
-        const int nmin = S.n_min, nmax = S.n_max;
+        const int nmax = S.n_max;
         if (S.lod_mode == PBF_LOD_EXPLICIT) {
             L = lev_by_id[id[s]];
         } else if (S.lod_mode == PBF_LOD_DTC) {
@@ -829,39 +829,28 @@ __device__ bool tile_tables(const TileLoc &t, const uint32_t *__restrict__ cell_
 
 // copy the staged rows of `src` into LDS, plus the far-away entry at
 // kFarCode that pads neighbour groups (all threads; ends with a barrier).
-// Wave w copies rows w, w + nw, ...: the first 64 entries of kStageBatch
-// of its rows are loaded together, so the wave waits once for all of them;
-// rows longer than 64 entries finish row by row.
-constexpr int kStageBatch = 5;
+// Wave w copies rows w, w + nw, ...: every 64-entry piece of a row is one
+// global-to-LDS load (gfx950 global_load_lds_dwordx4: lane L of the piece
+// lands 16 L bytes past the piece's LDS base), all of a wave's pieces are
+// issued before it waits once, and no data passes through registers.  The
+// caller has checked that the rows fit (tb.base[kStageRows] <= kStageCap),
+// so every written entry lies inside the stage.
+using lds_void = __attribute__((address_space(3))) void;
 __device__ __forceinline__ void tile_stage(const TileTables &tb, const float4 *__restrict__ src,
                                            float4 *__restrict__ stage)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (threadIdx.x == 0) stage[kFarCode] = make_float4(kFar, kFar, kFar, 0.f);
-    for (int r0 = wave; r0 < kStageRows; r0 += kStageBatch * nw) {
-        float4 v[kStageBatch];
-        uint32_t dst[kStageBatch];
-        bool on[kStageBatch];
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j) {
-            const int r = min(r0 + j * nw, kStageRows - 1);
-            const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0;
-            on[j] = r0 + j * nw < kStageRows && (uint32_t)lane < len;
-            dst[j] = tb.base[r] + (uint32_t)lane;
-            v[j] = on[j] ? src[g0 + (uint32_t)lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j)
-            if (on[j]) stage[dst[j]] = v[j];
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j) {
-            const int r = r0 + j * nw;
-            if (r < kStageRows) {
-                const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0, b0 = tb.base[r];
-                for (uint32_t e = (uint32_t)lane + 64u; e < len; e += 64) stage[b0 + e] = src[g0 + e];
-            }
+    for (int r = wave; r < kStageRows; r += nw) {
+        const uint32_t g0 = tb.bnd[r][0], len = tb.bnd[r][kStageEdge] - g0, b0 = tb.base[r];
+        for (uint32_t c = 0; c < len; c += 64) {
+            if (c + lane < len)
+                __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + g0 + c + lane),
+                                                 (lds_void *)(stage + b0 + c), 16, 0, 0);
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces are in LDS
     __syncthreads();
 }
 
