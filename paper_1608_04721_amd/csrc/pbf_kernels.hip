@@ -1397,13 +1397,9 @@ __device__ __forceinline__ void for_each_neighbour(const TileTables &tb,
     // group (group 0 exists for every p), so every load is unconditional
     const uint32_t last = cnt ? (cnt - 1u) >> 3 : 0u;
     const uint32_t stride = (uint32_t)n;  // groups of one particle are n entries apart
-    const uint4 *__restrict__ gp = nbr + p + (last ? stride : 0u);  // group min(1, last)
-    for (uint32_t q = 0; q < cnt; q += 8) {
-        const uint4 vn = *gp;
-        gp += (q >> 3) + 2u <= last ? stride : 0u;
-        const uint32_t cc[8] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16,
-                                v.z & 0xffffu, v.z >> 16, v.w & 0xffffu, v.w >> 16};
-        v = vn;
+    auto eval = [&](const uint4 &g, uint32_t q) {
+        const uint32_t cc[8] = {g.x & 0xffffu, g.x >> 16, g.y & 0xffffu, g.y >> 16,
+                                g.z & 0xffffu, g.z >> 16, g.w & 0xffffu, g.w >> 16};
         float4 xj[8];
         if (FITS) {
 #pragma unroll
@@ -1420,6 +1416,14 @@ __device__ __forceinline__ void for_each_neighbour(const TileTables &tb,
 #pragma unroll
             for (int u = 0; u < 8; ++u) f(xj[u]);
         }
+    };
+    const uint4 *__restrict__ gp = nbr + p + (last ? stride : 0u);  // group min(1, last)
+    for (uint32_t q = 0; q < cnt; q += 8) {
+        const uint4 vn = *gp;
+        gp += (q >> 3) + 2u <= last ? stride : 0u;
+        const uint4 g = v;
+        v = vn;
+        eval(g, q);
     }
 }
 
