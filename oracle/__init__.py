@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("dims", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
                 ("hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("mass", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double),
-                ("g", ctypes.c_double * 3), ("unilateral", ctypes.c_int32)]
+                ("g", ctypes.c_double * 3), ("unilateral", ctypes.c_int32),
+                ("cohesion", ctypes.c_double)]
 
 
 class Lod(ctypes.Structure):
@@ -116,6 +117,10 @@ def lib():
         L.orc_cell_keys.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p]
         L.orc_counting_sort.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
+        L.orc_cohesion_spline.restype = ctypes.c_double
+        L.orc_cohesion_spline.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_cohesion_accel.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         L.orc_set_threads.argtypes = [ctypes.c_int32]
         L.orc_get_threads.restype = ctypes.c_int32
         _lib = L
@@ -136,6 +141,26 @@ def get_threads() -> int:
 
 def poly6(r2: float, h: float) -> float:
     return float(lib().orc_poly6(float(r2), float(h)))
+
+
+def cohesion_spline(r: float, h: float) -> float:
+    """The cohesion kernel C(r) of the force-based cohesion option."""
+    return float(lib().orc_cohesion_spline(float(r), float(h)))
+
+
+def cohesion_accel(scene, x, off, ids) -> np.ndarray:
+    """Cohesion accelerations at positions x (n x 3) over the neighbour
+    sets given as CSR (off[n+1], ids in particle-ID order)."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    p = params(scene, n=x.shape[0])
+    off = np.ascontiguousarray(off, np.int64)
+    ids = np.ascontiguousarray(ids, np.int32)
+    a = np.zeros_like(x)
+    rc = lib().orc_cohesion_accel(ctypes.byref(p), x.ctypes.data, off.ctypes.data,
+                                  ids.ctypes.data if ids.size else None, a.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_cohesion_accel failed ({rc})")
+    return a
 
 
 def spiky_grad(d, h: float) -> np.ndarray:
@@ -159,6 +184,7 @@ def params(scene, n=None, n_min=None, n_max=None) -> Params:
     p.h, p.rho0, p.mass = float(scene.h), float(scene.rho0), float(scene.mass)
     p.eps, p.dt = float(scene.eps), float(scene.dt)
     p.unilateral = int(bool(getattr(scene, "unilateral", False)))
+    p.cohesion = float(getattr(scene, "cohesion", 0.0))
     return p
 
 

@@ -56,6 +56,19 @@
  *     (Section 4.1).
  *   - Unilateral density constraint (an option; the variant named at the
  *     end of Section 7's setup): C_i = max(rho_i/rho0 - 1, 0).
+ *   - Force-based cohesion (an option named beside it, taken from the
+ *     works the paper cites there: the cohesion kernel of Akinci et al.
+ *     2013).  Particle i gets the acceleration
+ *       a_i = -gamma m sum_j C(|x_i - x_j|) (x_i - x_j) / |x_i - x_j|
+ *     with C(r) = 32/(pi h^9) (h - r)^3 r^3 for h/2 < r <= h,
+ *     32/(pi h^9) (2 (h - r)^3 r^3 - h^6/64) for 0 < r <= h/2, else 0.
+ *     It is an external force of Fig. 7's first loop, evaluated at the
+ *     positions x at the start of the step over the neighbour sets N_i
+ *     that the second loop finds (the sets at x are not known before the
+ *     search); once the sets are known it is applied to the prediction,
+ *     x*_i += dt^2 a_i (clamped into the box), which is what adding dt a_i
+ *     to v_i in the first loop would have given.  The keys and the sets
+ *     come from x* before this shift.
  * Neighbour sums run in ascending particle-ID order, so results do not
  * depend on any storage order.
  */
@@ -79,6 +92,7 @@ typedef struct {
     double h, rho0, mass, eps, dt;
     double g[3];
     int32_t unilateral;     /* 1: C_i = max(rho_i / rho0 - 1, 0) (resists compression only) */
+    double cohesion;        /* gamma >= 0 of the force-based cohesion; 0: none */
 } orc_params;
 
 typedef struct {
@@ -663,10 +677,47 @@ int orc_levels(const orc_params *p, const orc_lod *lod, const double *x, int32_t
 static int check_params(const orc_params *p)
 {
     if (p->n < 0 || p->n_min < 1 || p->n_max < p->n_min || !(p->h > 0) || !(p->rho0 > 0) ||
-        !(p->mass > 0) || !(p->eps >= 0) || !(p->dt > 0))
+        !(p->mass > 0) || !(p->eps >= 0) || !(p->dt > 0) || !(p->cohesion >= 0) ||
+        !(p->cohesion < INFINITY))
         return ORC_ERR_ARG;
     for (int d = 0; d < 3; ++d)
         if (p->dims[d] < 1 || !(p->hi[d] >= p->lo[d])) return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+/* Cohesion kernel C(r) of the force-based cohesion (see the readings). */
+double orc_cohesion_spline(double r, double h)
+{
+    if (!(r > 0.0) || r > h) return 0.0;
+    const double c = 32.0 / (M_PI * pow(h, 9));
+    const double t = (h - r) * (h - r) * (h - r) * r * r * r;
+    return 2.0 * r > h ? c * t : c * (2.0 * t - pow(h, 6) / 64.0);
+}
+
+/* Cohesion acceleration of particle i at the positions x over its
+ * neighbour set ids[0..cnt) (ascending IDs). */
+static void cohesion_of(const orc_params *p, const double *x, int32_t i, const int32_t *ids,
+                        int64_t cnt, double a[3])
+{
+    a[0] = a[1] = a[2] = 0.0;
+    const double *xi = x + 3 * (int64_t)i;
+    for (int64_t e = 0; e < cnt; ++e) {
+        const double *xj = x + 3 * (int64_t)ids[e];
+        const double d[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(r > 0.0)) continue;  /* coincident particles: no direction, no force */
+        const double f = -p->cohesion * p->mass * orc_cohesion_spline(r, p->h) / r;
+        for (int k = 0; k < 3; ++k) a[k] += f * d[k];
+    }
+}
+
+/* The accelerations themselves (test access): a[n*3] from x over the
+ * CSR sets (off[n+1], ids). */
+int orc_cohesion_accel(const orc_params *p, const double *x, const int64_t *off, const int32_t *ids,
+                       double *a)
+{
+    if (!p || p->n < 0 || !(p->h > 0) || !(p->mass > 0) || !(p->cohesion >= 0)) return ORC_ERR_ARG;
+    for (int32_t i = 0; i < p->n; ++i) cohesion_of(p, x, i, ids + off[i], off[i + 1] - off[i], a + 3 * (int64_t)i);
     return ORC_OK;
 }
 
@@ -766,6 +817,19 @@ int orc_apbf_step_contacts(const orc_params *p, const orc_lod *lod, const orc_co
         if (tr->perm) memcpy(tr->perm, perm, sizeof(int32_t) * (size_t)n);
         copy_trace_neighbours(p, tr, off, ids);
         if (tr->xs_iter) memcpy(tr->xs_iter, xs, sizeof(double) * n3);
+    }
+
+    if (p->cohesion > 0.0) {
+        /* the cohesion force of the first loop, at x over the sets just found */
+        double *acc = (double *)malloc(sizeof(double) * (n3 ? n3 : 1));
+        if (!acc) { rc = ORC_ERR_MEM; goto done; }
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int32_t i = 0; i < n; ++i) cohesion_of(p, x, i, ids + off[i], off[i + 1] - off[i], acc + 3 * (int64_t)i);
+        for (int32_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) xs[3 * (int64_t)i + d] += p->dt * p->dt * acc[3 * (int64_t)i + d];
+            clamp_box(p, xs + 3 * (int64_t)i);
+        }
+        free(acc);
     }
 
     if (oc && oc->count > 0) {

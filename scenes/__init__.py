@@ -109,6 +109,8 @@ class Scene:
     extra_cameras: tuple = ()
     auto_range: bool = False
     unilateral: bool = False
+    # coefficient gamma of the force-based cohesion (0: none)
+    cohesion: float = 0.0
 
     def __post_init__(self):
         self.x0 = np.ascontiguousarray(self.x0, dtype=F32).reshape(-1, 3)
