@@ -29,6 +29,7 @@
  *     prediction and after every update; optional solid obstacles add the
  *     contact finding, pre-stabilisation and contact response of Fig. 7
  *     (pbf_batch_set_obstacles);
+ *   - optional force-based cohesion (pbf_batch_set_cohesion);
  *   - iteration k = 0..n_max-1 corrects particle i only while k < N_i.
  *
  * Conventions (every entry point):
@@ -251,6 +252,24 @@ pbf_status pbf_batch_set_lod(pbf_ctx *ctx, int32_t scene, const pbf_lod_desc *lo
  * any scene adds one per-particle pass after the neighbour search and keeps
  * a byte per particle (the contact set of the last step). */
 pbf_status pbf_batch_set_obstacles(pbf_ctx *ctx, int32_t scene, const pbf_contact_desc *desc);
+/* Force-based cohesion of one scene (0-based): the option the paper names
+ * beside the unilateral density constraint at the end of Section 7's setup,
+ * by reference to the works it cites there.  Reading (the same in the test
+ * suite's FP64 oracle): particle i gets the acceleration
+ *   a_i = -gamma m sum_{j in N_i} C(|x_i - x_j|) (x_i - x_j) / |x_i - x_j|,
+ *   C(r) = 32/(pi h^9) (h - r)^3 r^3          for h/2 < r <= h,
+ *          32/(pi h^9) (2 (h - r)^3 r^3 - h^6/64) for 0 < r <= h/2, else 0
+ * (the cohesion kernel of Akinci et al. 2013), an external force of Fig. 7's
+ * first loop evaluated at the positions x at the start of the step over the
+ * neighbour sets N_i found at the predicted positions; once the sets are
+ * known it is applied to the prediction, x*_i += dt^2 a_i, clamped into the
+ * box (what adding dt a_i to v_i in the first loop gives).  gamma >= 0 and
+ * finite (0 removes it), in units of m^3 / (kg s^2) with m the particle mass;
+ * applies from the next step.  Anything else, or a bad scene index, gives
+ * PBF_ERR_INVALID_ARG and changes nothing.  A context with cohesion in any
+ * scene adds one tile pass after the neighbour search; rollouts reject such
+ * contexts (the reverse mode does not differentiate it). */
+pbf_status pbf_batch_set_cohesion(pbf_ctx *ctx, int32_t scene, float gamma);
 /* Positions of one scene, float[3 * n_scene] in its ID order. */
 pbf_status pbf_batch_read_positions(pbf_ctx *ctx, int32_t scene, float *out,
                                     int32_t out_on_device);

@@ -123,6 +123,8 @@ class Sim:
                 if getattr(s, "obstacles", ()) or getattr(s, "stab_iters", 0):
                     self.set_obstacles(s.obstacles, stab_iters=getattr(s, "stab_iters", 0),
                                        stab_set=getattr(s, "stab_s", 1), scene=i)
+                if getattr(s, "cohesion", 0.0):
+                    self.set_cohesion(s.cohesion, scene=i)
 
     # ------------------------------------------------------------ helpers
     def _check(self, st, what):
@@ -201,6 +203,11 @@ class Sim:
         d.stab_iters, d.stab_set = int(stab_iters), int(stab_set)
         self._check(self._lib.pbf_batch_set_obstacles(self._ctx, int(scene), ctypes.byref(d)),
                     "pbf_batch_set_obstacles")
+
+    def set_cohesion(self, gamma: float, scene: int = 0):
+        """Force-based cohesion coefficient of one scene (0 removes it)."""
+        self._check(self._lib.pbf_batch_set_cohesion(self._ctx, int(scene), float(gamma)),
+                    "pbf_batch_set_cohesion")
 
     def step(self, n_steps: int = 1):
         self._check(self._lib.pbf_step(self._ctx, int(n_steps)), "pbf_step")

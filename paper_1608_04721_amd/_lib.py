@@ -90,6 +90,7 @@ SIGNATURES = {
     "pbf_batch_create": (c_i32, [c_i32, P(PbfParams), c_vp, c_vp, c_i32, c_vp, P(CTX)]),
     "pbf_batch_set_lod": (c_i32, [CTX, c_i32, P(PbfLodDesc)]),
     "pbf_batch_set_obstacles": (c_i32, [CTX, c_i32, P(PbfContactDesc)]),
+    "pbf_batch_set_cohesion": (c_i32, [CTX, c_i32, c_f32]),
     "pbf_batch_read_positions": (c_i32, [CTX, c_i32, c_vp, c_i32]),
     "pbf_get_counts": (c_i32, [CTX, P(c_i32), P(c_i64)]),
     "pbf_set_memory_limit": (c_i32, [c_i64]),

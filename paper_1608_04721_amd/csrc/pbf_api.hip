@@ -291,7 +291,7 @@ bool fixed_shape(int k)
 int max_block(int k)
 {
     if (k == K_NEIGHBOURS) return kNbrThreads;
-    if (k == K_LAMBDA || k == K_UPDATE) return kTileThreads;
+    if (k == K_LAMBDA || k == K_UPDATE || k == K_COHESION) return kTileThreads;
     return 1024;
 }
 
@@ -913,6 +913,32 @@ pbf_status pbf_batch_set_obstacles(pbf_ctx *c, int32_t scene, const pbf_contact_
     return PBF_OK;
 }
 
+pbf_status pbf_batch_set_cohesion(pbf_ctx *c, int32_t scene, float gamma)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (scene < 0 || scene >= c->n_scenes) return fail(c, PBF_ERR_INVALID_ARG, "bad scene index");
+    if (!(gamma >= 0.f) || !std::isfinite(gamma))
+        return fail(c, PBF_ERR_INVALID_ARG, "cohesion must be finite and >= 0");
+    const pbf_params &p = c->params[scene];
+    SceneDev s = c->scenes[scene];
+    const double h = p.h, pi = 3.14159265358979323846;
+    s.cohesion = gamma;
+    s.c_coh = (float)((double)gamma * p.mass * 32.0 * (double)p.dt * p.dt / (pi * std::pow(h, 9)));
+    if (gamma > 0.f && !(std::isfinite(s.c_coh) && s.c_coh > 0.f))
+        return fail(c, PBF_ERR_INVALID_ARG, "cohesion factor out of float range for this scene");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    bool on = false;
+    for (int k = 0; k < c->n_scenes; ++k) on = on || (k == scene ? s : c->scenes[k]).c_coh > 0.f;
+    c->scenes[scene] = s;
+    c->roll_valid = false;
+    if (on != c->b.cohesion_on) drop_graphs(c);  // the step's launches change
+    c->b.cohesion_on = on;
+    HIPCHK(c, hipMemcpyAsync((void *)c->b.scenes, c->scenes.data(), sizeof(SceneDev) * c->scenes.size(),
+                             hipMemcpyHostToDevice, c->stream), "upload scenes");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return PBF_OK;
+}
+
 pbf_status pbf_step(pbf_ctx *c, int32_t n_steps)
 {
     if (!c) return PBF_ERR_INVALID_ARG;
@@ -1350,6 +1376,8 @@ pbf_status pbf_rollout_forward(pbf_ctx *c, int32_t n_steps, int32_t ckpt_every)
         return fail(c, PBF_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
     if (c->b.contacts_on)
         return fail(c, PBF_ERR_INVALID_ARG, "the rollout does not differentiate obstacle contacts");
+    if (c->b.cohesion_on)
+        return fail(c, PBF_ERR_INVALID_ARG, "the rollout does not differentiate the cohesion force");
     for (const pbf_params &p : c->params)
         if (p.flags & PBF_FLAG_UNILATERAL)
             return fail(c, PBF_ERR_INVALID_ARG,

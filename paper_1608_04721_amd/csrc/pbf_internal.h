@@ -91,6 +91,9 @@ struct SceneDev {
     float rng[kMaxCameras][2];
     uint32_t range_off;
     float c_floor;  // lower bound of C_i: 0 (unilateral) or -infinity
+    // force-based cohesion: gamma, and the factor gamma m 32 dt^2 / (pi h^9)
+    // of the prediction's shift (0: none)
+    float cohesion, c_coh;
 };
 
 // Device fault bits, latched in a device word.
@@ -120,6 +123,7 @@ enum Kernel : int {
     K_COMMIT,
     K_CONTACTS,
     K_LOD_RANGE,
+    K_COHESION,
     K_COUNT
 };
 
@@ -202,6 +206,7 @@ struct StepBuffers {
     uint32_t n_depth;        // their pixels in total (0: no DTVS scene)
     uint8_t *contact;        // [n] contacts found this step, slot order (bit o: obstacle o)
     bool contacts_on;        // some scene has obstacles or pre-stabilisation
+    bool cohesion_on;        // some scene has force-based cohesion
     uint32_t *range;         // automatic distance ranges (min, max float bits per camera)
     uint32_t n_range;        // their words (0: no scene with an automatic range)
 };

@@ -36,13 +36,13 @@ const char *const kKernelNames[K_COUNT] = {
     "depth",        "lod_predict",  "scan_reduce", "scan_top",     "scan_apply",  "sort_scatter",
     "sort_finish",  "tile_prepare", "level_count", "level_scan",  "level_scatter",
     "tile_tables",  "neighbours",  "lambda",       "update",      "commit",       "contacts",
-    "lod_range"};
+    "lod_range",    "cohesion"};
 
 const int kDefaultBlock[K_COUNT] = {256,          256,          kScanBlock,   1024,         kScanBlock,
                                     256,          256,          256,          kLevelBlock,
                                     1024,         kLevelBlock,  1024,         kNbrThreads,
                                     kTileThreads, kTileThreads, 256,          256,
-                                    256};
+                                    256,          kTileThreads};
 
 namespace {
 
@@ -1625,6 +1625,73 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
                                            p0, nown, first, last, hd);
 }
 
+// ------------------------------------------------ force-based cohesion
+// The cohesion option's acceleration (see pbf_batch_set_cohesion) of every
+// own particle of a tile, at the positions x at the start of the step (slot
+// order, staged like x*) over the step's neighbour lists, applied to the
+// prediction: x*_i += -c_coh sum_j P(r) d/r, P = (h - r)^3 r^3 (2 r > h) or
+// 2 (h - r)^3 r^3 - h^6/64, clamped into the box.  Pair terms are
+// branch-free: beyond h (and for the far-away padding entry) h - r clamps to
+// zero, and coincident particles (d = 0) give zero.
+template <bool FITS>
+__device__ __forceinline__ void tile_cohesion(const SceneDev &S, const TileTables &tb,
+                                              const float4 *__restrict__ stage,
+                                              const float4 *__restrict__ x, float4 *__restrict__ xs,
+                                              int64_t n, const uint4 *__restrict__ nbr,
+                                              const uint32_t *__restrict__ pmeta,
+                                              const uint32_t *__restrict__ pslot, uint32_t p0,
+                                              uint32_t first, uint32_t last)
+{
+    const float h = S.h, half = 0.5f * S.h, q64 = S.h6 * (1.f / 64.f), c = S.c_coh;
+    for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
+        const size_t p = p0 + pl;
+        const uint32_t meta = pmeta[p];
+        const uint32_t i = pslot[p];  // independent loads, issued together
+        const float4 xi = FITS ? stage[meta_self(meta)] : x[i];
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        for_each_neighbour<FITS>(tb, stage, x, nbr, n, p, meta & kMetaCount, nbr[p], [&](const float4 &xj) {
+            const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, kTinyR2));
+            const float r = r2 * ir;
+            const float u = fmaxf(h - r, 0.f) * r;  // 0 beyond h (even for the far entry)
+            const float t = u * u * u;
+            const float P = r > half ? t : 2.f * t - q64;
+            const float f = P * ir;
+            ax += f * dx;
+            ay += f * dy;
+            az += f * dz;
+        });
+        const float4 s = xs[i];
+        xs[i] = make_float4(clampf(s.x - c * ax, S.lo[0], S.hi[0]), clampf(s.y - c * ay, S.lo[1], S.hi[1]),
+                            clampf(s.z - c * az, S.lo[2], S.hi[2]), s.w);
+    }
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kTileThreads) void k_cohesion(
+    const SceneDev *__restrict__ sc, const uint4 *__restrict__ tile_rec,
+    const uint32_t *__restrict__ tile_ge, const uint32_t *__restrict__ rows,
+    const float4 *__restrict__ x, float4 *__restrict__ xs, int64_t n,
+    const uint4 *__restrict__ nbr, const uint32_t *__restrict__ pmeta,
+    const uint32_t *__restrict__ pslot, uint32_t tx)
+{
+    __shared__ TileTables tb;
+    __shared__ float4 stage[kStageEntries];
+    uint32_t slot;  // every tile with particles
+    if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[1], slot)) return;
+    const uint4 rec = tile_rec[slot];  // tile, first p, own particles, scene
+    const SceneDev &S = sc[rec.w];
+    if (!(S.c_coh != 0.f)) return;  // uniform: scenes without cohesion
+    const uint32_t p0 = rec.y, nown = rec.z;
+    uint32_t first = 0, last = nown;
+    if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
+    if (stage_rows(rows, slot, x, tb, stage))
+        tile_cohesion<true>(S, tb, stage, x, xs, n, nbr, pmeta, pslot, p0, first, last);
+    else
+        tile_cohesion<false>(S, tb, stage, x, xs, n, nbr, pmeta, pslot, p0, first, last);
+}
+
 // ------------------------------------------------ average density
 // Cell keys and histogram tickets of the current positions (no prediction):
 // the start of a fresh neighbour search for the density measure.
@@ -1913,6 +1980,10 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     LAUNCH(K_NEIGHBOURS, TX * SPLIT, bs[K_NEIGHBOURS], nbr_kernel, b.scenes, b.tile_scene,
            b.tile_order, b.tile_ge, b.tile_start, b.cell_start, b.xs[0], b.lvl[nxt], n, b.nbr_cap,
            b.nbr, b.pmeta, b.pslot, b.tile_count, b.tile_rows, b.err, TX, b.tile_rec);
+    if (b.cohesion_on)  // the cohesion force, before contact finding (it is part of the prediction)
+        LAUNCH(K_COHESION, TX * SPLIT, bs[K_COHESION], split ? k_cohesion<true> : k_cohesion<false>,
+               b.scenes, b.tile_rec, b.tile_ge, b.tile_rows, b.x[nxt], b.xs[0], n, b.nbr, b.pmeta,
+               b.pslot, TX);
     if (ct)
         LAUNCH(K_CONTACTS, blocks_for(n, bs[K_CONTACTS]), bs[K_CONTACTS], k_contacts, n, b.scenes,
                b.x[nxt], b.xs[0], b.lvl[nxt], b.contact);

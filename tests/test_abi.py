@@ -102,6 +102,7 @@ def test_null_arguments_rejected(lib):
     assert lib.pbf_set_graph(None, 1) == _lib.PBF_ERR_INVALID_ARG
     assert lib.pbf_density(None, None, None, 0) == _lib.PBF_ERR_INVALID_ARG
     assert lib.pbf_density_noalloc(None, None, None, 0) == _lib.PBF_ERR_INVALID_ARG
+    assert lib.pbf_batch_set_cohesion(None, 0, 1.0) == _lib.PBF_ERR_INVALID_ARG
     lib.pbf_destroy(None)
 
 
