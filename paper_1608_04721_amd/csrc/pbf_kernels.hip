@@ -1220,21 +1220,26 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         const float4 xi = FITS ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
         const size_t p = (size_t)p0 + first + pr;
         uint32_t cnt = 0;
-        const uint32_t cap8 = ((uint32_t)cap + 7u) & ~7u;  // codes that have room
-        // each code is stored as it is found, 16 bits at a time; the pointer
-        // steps one code inside a group and on to the particle's next group
-        // (n groups further) after the eighth code
-        char *__restrict__ out = reinterpret_cast<char *>(nbr + p);
-        const uint32_t jump = (uint32_t)(16 * n - 14);  // bytes from the last code of a group
-        auto store = [&](uint32_t code) {  // no capacity test
-            *reinterpret_cast<uint16_t *>(out) = (uint16_t)code;
-            ++cnt;
-            out += (cnt & 7u) ? 2u : jump;
-        };
+        const uint32_t room = ((uint32_t)cap + 7u) >> 3;  // groups that have room
+        // The particle's current group of eight codes is built in four
+        // registers: each code enters at the top and the group shifts down by
+        // 16 bits, so after the eighth the first code found sits in the low
+        // half of the first word, the order of the stored u16 array.  A full
+        // group is written with one 16-byte store, the particle's next group
+        // n groups further on: one write request per eight codes instead of
+        // one per code, which bound the build when each 16-bit code was
+        // stored as it was found.
+        uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
         auto put = [&](uint32_t code) {
-            if (cnt < cap8) *reinterpret_cast<uint16_t *>(out) = (uint16_t)code;
+            w0 = __builtin_amdgcn_alignbit(w1, w0, 16);
+            w1 = __builtin_amdgcn_alignbit(w2, w1, 16);
+            w2 = __builtin_amdgcn_alignbit(w3, w2, 16);
+            w3 = __builtin_amdgcn_alignbit(code, w3, 16);
             ++cnt;
-            out += (cnt & 7u) ? 2u : jump;
+            if ((cnt & 7u) == 0u) {
+                const uint32_t g = (cnt >> 3) - 1u;
+                if (g < room) nbr[p + (size_t)g * (size_t)n] = make_uint4(w0, w1, w2, w3);
+            }
         };
 #pragma unroll 1
         for (int win = 0; win < 9; ++win) {
@@ -1270,15 +1275,7 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                 m = __builtin_bitreverse32(m) >> (32u - tested);
                 if (cl < 32u) m &= (1u << cl) - 1u;
                 if (ja + c0 <= i && i < ja + c0 + cl) m &= ~(1u << (i - ja - c0));  // not itself
-                // ... then its hits become codes, in candidate order (without
-                // a capacity test per code while the chunk's hits have room)
-                if (FITS && cnt + (uint32_t)__popc(m) <= cap8) {
-                    const uint32_t lc = l0 + c0;
-                    while (m) {
-                        store(lc + (uint32_t)(__ffs(m) - 1));
-                        m &= m - 1u;
-                    }
-                }
+                // ... then its hits become codes, in candidate order
                 while (m) {
                     const uint32_t c = c0 + (uint32_t)(__ffs(m) - 1);
                     m &= m - 1u;
@@ -1295,9 +1292,11 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         if (cnt > (uint32_t)cap) {
             bad |= ERR_NEIGHBOUR_CAP;
             cnt = (uint32_t)cap & ~7u;  // only whole stored groups are valid
-        } else if (FITS && (cnt & 7u)) {
+        } else if (cnt & 7u) {
+            // complete and store the last group: on the LDS path its unused
+            // codes name the far-away entry (the HBM path reads only cnt codes)
             const uint32_t keep = cnt;
-            while (cnt & 7u) put(kFarCode);  // pad the last group (the HBM path reads only cnt codes)
+            while (cnt & 7u) put(FITS ? kFarCode : 0u);
             cnt = keep;
         }
         pslot[p] = i;
