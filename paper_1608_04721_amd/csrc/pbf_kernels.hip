@@ -1218,6 +1218,14 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         int lx = 1;
         while (lx < kTileEdge && tb.bnd[r][lx + 1] <= i) ++lx;  // x-cell of i, 1..kTileEdge
         const float4 xi = FITS ? stage[tb.base[r] + (i - tb.bnd[r][0])] : xs[i];
+        // LDS path: the stage holds positions relative to the block's centre
+        // with |x|^2 in .w, so |x_i - x_j|^2 - h^2 = |x_j|^2 + (|x_i|^2 - h^2)
+        // - 2 x_i.x_j: one add and three FMAs per candidate.  Staged
+        // positions lie within 3 h of the centre on each axis, so |x|^2 <=
+        // 27 h^2 and the expanded form's rounding stays near 1e-5 of h^2:
+        // only pairs at the radius to that precision can be decided
+        // differently from the direct form.
+        const float ax = -2.f * xi.x, ay = -2.f * xi.y, az = -2.f * xi.z, ci = xi.w - h2;
         const size_t p = (size_t)p0 + first + pr;
         uint32_t cnt = 0;
         const uint32_t room = ((uint32_t)cap + 7u) >> 3;  // groups that have room
@@ -1264,9 +1272,13 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                         xj[u] = FITS ? sp[u] : xs[min((int64_t)(ja + c0 + c + u), n - 1)];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        if (FITS) asm volatile("" : : "v"(xj[u].w));  // 16-byte LDS reads
-                        const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
-                        const float e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -h2)));  // < 0: inside
+                        float e;  // < 0: inside
+                        if (FITS) {
+                            e = fmaf(az, xj[u].z, fmaf(ay, xj[u].y, fmaf(ax, xj[u].x, xj[u].w + ci)));
+                        } else {
+                            const float dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
+                            e = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -h2)));
+                        }
                         m = __builtin_amdgcn_alignbit(m, __float_as_uint(e), 31);
                     }
                 }
@@ -1352,6 +1364,19 @@ __global__ __launch_bounds__(kNbrThreads) __attribute__((amdgpu_waves_per_eu(8))
     uint32_t bad;
     if (fits) {
         tile_stage(tb, xs, stage);
+        // positions relative to the centre of the staged block, with their
+        // squared length in .w, for the expanded distance test
+        const SceneDev &S = *t.S;
+        const float c0 = S.lo[0] + (float)(t.tx * kTileEdge + kStageEdge / 2 - 1) * S.h;
+        const float c1 = S.lo[1] + (float)(t.ty * kTileEdge + kStageEdge / 2 - 1) * S.h;
+        const float c2 = S.lo[2] + (float)(t.tz * kTileEdge + kStageEdge / 2 - 1) * S.h;
+        const uint32_t total = tb.base[kStageRows];
+        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+            const float4 v = stage[e];
+            const float rx = v.x - c0, ry = v.y - c1, rz = v.z - c2;
+            stage[e] = make_float4(rx, ry, rz, fmaf(rz, rz, fmaf(ry, ry, rx * rx)));
+        }
+        __syncthreads();
         bad = tile_neighbours<true>(tb, stage, xs, h2, p0, n, cap, lvl, nbr, pmeta, pslot, first, last,
                                     rank01, rank23);
     } else {
