@@ -1227,7 +1227,7 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         // differently from the direct form.
         const float ax = -2.f * xi.x, ay = -2.f * xi.y, az = -2.f * xi.z, ci = xi.w - h2;
         const size_t p = (size_t)p0 + first + pr;
-        uint32_t cnt = 0;
+
         const uint32_t room = ((uint32_t)cap + 7u) >> 3;  // groups that have room
         // The particle's current group of eight codes is built in four
         // registers: each code enters at the top and the group shifts down by
@@ -1237,16 +1237,17 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
         // n groups further on: one write request per eight codes instead of
         // one per code, which bound the build when each 16-bit code was
         // stored as it was found.
-        uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        // free: slots left in the current group (8..1); full: groups completed
+        uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, free = 8, full = 0;
         auto put = [&](uint32_t code) {
             w0 = __builtin_amdgcn_alignbit(w1, w0, 16);
             w1 = __builtin_amdgcn_alignbit(w2, w1, 16);
             w2 = __builtin_amdgcn_alignbit(w3, w2, 16);
             w3 = __builtin_amdgcn_alignbit(code, w3, 16);
-            ++cnt;
-            if ((cnt & 7u) == 0u) {
-                const uint32_t g = (cnt >> 3) - 1u;
-                if (g < room) nbr[p + (size_t)g * (size_t)n] = make_uint4(w0, w1, w2, w3);
+            if (--free == 0u) {
+                if (full < room) nbr[p + (size_t)full * (size_t)n] = make_uint4(w0, w1, w2, w3);
+                ++full;
+                free = 8;
             }
         };
 #pragma unroll 1
@@ -1301,15 +1302,14 @@ __device__ __forceinline__ uint32_t tile_neighbours(const TileTables &tb, const 
                 }
             }
         }
+        uint32_t cnt = 8u * full + (8u - free);
         if (cnt > (uint32_t)cap) {
             bad |= ERR_NEIGHBOUR_CAP;
             cnt = (uint32_t)cap & ~7u;  // only whole stored groups are valid
-        } else if (cnt & 7u) {
+        } else if (free != 8u) {
             // complete and store the last group: on the LDS path its unused
             // codes name the far-away entry (the HBM path reads only cnt codes)
-            const uint32_t keep = cnt;
-            while (cnt & 7u) put(FITS ? kFarCode : 0u);
-            cnt = keep;
+            while (free != 8u) put(FITS ? kFarCode : 0u);
         }
         pslot[p] = i;
         pmeta[p] = make_meta(cnt, lvl[i], FITS ? tb.base[r] + (i - tb.bnd[r][0]) : 0u);
