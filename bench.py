@@ -533,7 +533,7 @@ def summarize_counters(root: Path) -> dict:
         if n["fetch"] and n["write"] and out["fetch_factor"]:
             out["bytes_per_dispatch"][k] = int(1024 * (cs["FETCH_SIZE"] / n["fetch"] / out["fetch_factor"] +
                                                        cs["WRITE_SIZE"] / n["write"] / out["write_factor"]))
-            out["dispatch_s"][k] = dur["fetch"] / n["fetch"]
+            out["dispatch_s"][k] = (dur["fetch"] + dur["write"]) / (n["fetch"] + n["write"])
         if n["sq1"] and cs.get("SQ_INSTS_VALU"):
             out["valu_issue"][k] = round(cs["SQ_INSTS_VALU"] / dur["sq1"] / VALU_PEAK_WAVE_INSTR, 4)
             if cs.get("SQ_WAVE_CYCLES") and n["sq2"]:
