@@ -1637,6 +1637,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     const uint32_t p0 = rec.y, nown = rec.z;
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
+    if (slot >= tile_ge[k + 1]) {
+        // the tile's highest level is k: its particles only copy across, so
+        // its neighbourhood is not staged
+        for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
+            const uint32_t meta = pmeta[p0 + pl], i = pslot[p0 + pl];
+            if ((int)meta_level(meta) == k) xs_out[i] = xs_in[i];
+        }
+        return;
+    }
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
     if (!stage_rows(rows, slot, xs_in, tb, stage))
         tile_update<false, CONTACTS, false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact,
