@@ -47,6 +47,9 @@ BYTES_PER_ACTIVE = {"lambda": 20.0, "update": 36.0}
 DESIGN_BYTES = {"lambda": {"per_active": 8.0 + 4.0 + 54.0},
                 "update": {"per_active": 8.0 + 16.0 + 54.0}}
 NBR_CAP = 256  # neighbour capacity of every tank run (APBF, DTVS, PBF): like for like
+# A PBF run that compresses the tank beyond NBR_CAP neighbours is repeated at
+# this capacity, and its entry says so (then it is not like for like).
+NBR_CAP_RETRY = 2 * NBR_CAP
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3  # published vector FP32 peak (counts dual-issue)
 
@@ -629,6 +632,16 @@ def main(argv=None):
                     out_pbf[N] = _timed_run(sim, steps, warm, stream, torch)
                 except PbfError as e:
                     out_pbf[N] = {"error": str(e)}
+            if "error" in out_pbf[N] and "capacity" in out_pbf[N]["error"]:
+                print(f"[bench] PBF N={N} again at capacity {NBR_CAP_RETRY}", file=sys.stderr, flush=True)
+                with Sim(scp, stream=stream, max_neighbours=NBR_CAP_RETRY) as sim:
+                    try:
+                        r = _timed_run(sim, steps, warm, stream, torch)
+                        r["neighbour_capacity"] = NBR_CAP_RETRY
+                        r["at_capacity_%d" % cap] = out_pbf[N]["error"]
+                        out_pbf[N] = r
+                    except PbfError as e:
+                        out_pbf[N]["error_at_capacity_%d" % NBR_CAP_RETRY] = str(e)
     print("[bench] profiling kernels", file=sys.stderr, flush=True)
     prof, pairs, active, _, design = _profile(sc, args.profile_steps, Sim, stream, cap)
     roof, kernels = _roofline(prof, pairs, active, design)
@@ -640,8 +653,14 @@ def main(argv=None):
                          ("pbf5", sc.with_lod(PBF_LOD_UNIFORM, n_min=5, n_max=5))):
             print(f"[bench] {name}: {sc.steps} steps from t = 0", file=sys.stderr, flush=True)
             full[name] = _full_run(s_, int(sc.steps), Sim, stream, torch, cap)
-        if "error" not in full["apbf"] and "error" not in full["pbf10"]:
-            full["speedup_vs_pbf10"] = round(full["pbf10"]["ms_per_step"] / full["apbf"]["ms_per_step"], 4)
+            if name != "apbf" and "error" in full[name] and "capacity" in full[name]["error"]:
+                r = _full_run(s_, int(sc.steps), Sim, stream, torch, NBR_CAP_RETRY)
+                r["neighbour_capacity"] = NBR_CAP_RETRY
+                r["at_capacity_%d" % cap] = {k: v for k, v in full[name].items() if k != "steps"}
+                full[name] = r
+        for ref in ("pbf10", "pbf5"):
+            if "error" not in full["apbf"] and "error" not in full[ref]:
+                full["speedup_vs_" + ref] = round(full[ref]["ms_per_step"] / full["apbf"]["ms_per_step"], 4)
         extra["tank_1m_100_steps"] = full
         # the 262,144-particle dam break, plain PBF with N = 10, 100 steps
         sd = scenes.dam_break_262k()
@@ -703,12 +722,14 @@ def main(argv=None):
                      "mean_levels": round(dtvs["mean_levels"], 4), "density": dtvs["density"]})
     line["dtvs"]["levels"] = "distance to the visible surface, 0..4 m -> 10..5, same camera"
     if out_pbf:
-        line["pbf"] = {str(N): ({"error": r["error"]} if "error" in r else
+        line["pbf"] = {str(N): ({k: v for k, v in r.items() if "error" in k} if "error" in r else
                                 {"ms_per_step": round(r["ms_per_step"], 4),
                                  "ms_median": round(r["ms_median"], 4),
                                  "value": round(r["value"], 1),
                                  "max_neighbours": r["max_neighbours"],
-                                 "density": r["density"]})
+                                 "density": r["density"],
+                                 **{k: v for k, v in r.items()
+                                    if k == "neighbour_capacity" or k.startswith("at_capacity")}})
                        for N, r in out_pbf.items()}
         for N in (10, 5):
             if "error" not in out_pbf[N]:
