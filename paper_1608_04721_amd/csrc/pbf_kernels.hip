@@ -1877,18 +1877,32 @@ __global__ void k_unpermute_scalar(int64_t n, const float *__restrict__ v,
 }
 
 // --------------------------------------------- velocity and position update
+// Each thread takes kCommitPer slots, blockDim.x apart, loaded together.
+constexpr int kCommitPer = 2;
+
 __global__ void k_commit(int64_t n, const SceneDev *__restrict__ sc, float4 *__restrict__ x,
                          float4 *__restrict__ v, const float4 *__restrict__ xs,
                          uint32_t *__restrict__ err)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const float4 xi = x[s];
-    const float4 p = xs[s];
-    const float dt = sc[__float_as_int(xi.w)].dt;
-    if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) atomicOr(err, ERR_NONFINITE);
-    v[s] = make_float4((p.x - xi.x) / dt, (p.y - xi.y) / dt, (p.z - xi.z) / dt, 0.f);
-    x[s] = make_float4(p.x, p.y, p.z, xi.w);
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kCommitPer + threadIdx.x;
+    float4 xi[kCommitPer], p[kCommitPer];
+#pragma unroll
+    for (int q = 0; q < kCommitPer; ++q) {
+        const int64_t s = base + (int64_t)q * blockDim.x;
+        if (s < n) {
+            xi[q] = x[s];
+            p[q] = xs[s];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kCommitPer; ++q) {
+        const int64_t s = base + (int64_t)q * blockDim.x;
+        if (s >= n) continue;
+        const float dt = sc[__float_as_int(xi[q].w)].dt;
+        if (!(isfinite(p[q].x) && isfinite(p[q].y) && isfinite(p[q].z))) atomicOr(err, ERR_NONFINITE);
+        v[s] = make_float4((p[q].x - xi[q].x) / dt, (p[q].y - xi[q].y) / dt, (p[q].z - xi[q].z) / dt, 0.f);
+        x[s] = make_float4(p[q].x, p[q].y, p[q].z, xi[q].w);
+    }
 }
 
 
@@ -2038,7 +2052,7 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
             (e = hipMemcpyAsync(rec->lvl, b.lvl[nxt], n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;
     }
-    LAUNCH(K_COMMIT, blocks_for(n, bs[K_COMMIT]), bs[K_COMMIT], k_commit, n, b.scenes, b.x[nxt],
+    LAUNCH(K_COMMIT, blocks_for(n, bs[K_COMMIT] * kCommitPer), bs[K_COMMIT], k_commit, n, b.scenes, b.x[nxt],
            b.v[nxt], b.xs[K & 1], b.err);
     return hipSuccess;
 }
