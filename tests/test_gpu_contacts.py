@@ -111,6 +111,33 @@ def test_multi_dam_break_steps_match_oracle(graph):
     assert touched > 50 and stabbed > 20
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_multi_dam_break_with_cohesion_matches_oracle(graph):
+    # the cohesion shift is part of the prediction, so contacts are searched
+    # from the shifted positions; the run checks that this order decides
+    # some contact sets (the oracle without cohesion finds others)
+    sc = dataclasses.replace(
+        _aimed_multi_dam(a=9, ny=10, box=(1.6, 1.0, 1.6), cone=(0.35, 0.5), n_min=2, n_max=6,
+                         stab_iters=2, stab_s=5), cohesion=1.0)
+    plain = dataclasses.replace(sc, cohesion=0.0)
+    touched, decided, moved = 0, 0, 0.0
+    with _sim(sc) as sim:
+        sim.set_graph(graph)
+        x, v = sc.x0, sc.v0
+        for step in range(12):
+            info = _compare_step(sc, sim, x, v)
+            x0, _, i0 = oracle.apbf_step(plain, x.astype(np.float64), v.astype(np.float64),
+                                         trace=True, mode=scenes.LOD_EXPLICIT, levels=info["levels"])
+            near = _near_bound(sc, info["xs_iter"][0]) | _near_bound(sc, i0["xs_iter"][0])
+            decided += int(((i0["contacts"] != info["contacts"]) & ~near).sum())
+            touched = max(touched, int(info["contacts"].sum()))
+            moved = max(moved, float(np.abs(sim.positions() - x0).max()))
+            x, v = sim.positions(), sim.velocities()
+    print(f"contacts up to {touched}, contact sets decided by cohesion {decided}, "
+          f"cohesion moved positions by up to {moved:.2e}")
+    assert touched > 30 and decided >= 3 and moved > 100 * pos_tol(sc)
+
+
 @pytest.mark.parametrize("kind,c,a", [(SPHERE, (0.0, 0.0, 0.0), (0.5, 0.0, 0.0)),
                                       (BOX, (0.0, 0.0, 0.0), (0.4, 0.5, 0.3)),
                                       (CONE, (0.0, 0.0, 0.0), (0.6, 0.55, 0.0))])
