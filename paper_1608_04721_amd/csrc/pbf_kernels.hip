@@ -1404,6 +1404,47 @@ __device__ __forceinline__ bool stage_rows(const uint32_t *__restrict__ rows, ui
     return fits;
 }
 
+// The same in two parts, for words of the saved tables that each thread has
+// already loaded (words threadIdx.x + q blockDim.x, see saved_row_words):
+// the tables depend only on the slot, so their load can leave together with
+// the tile's record.  put_rows stores them (before the caller issues loads
+// that depend on the record, so that the wait covers only these words);
+// stage_tables then stages `src` (all threads; ends with a barrier).
+constexpr int kRowHold = (kRowWords + 63) / 64;  // words per thread at 64 threads
+struct RowWords {
+    uint32_t w[kRowHold];
+};
+
+__device__ __forceinline__ RowWords saved_row_words(const uint32_t *__restrict__ rows, uint32_t slot)
+{
+    RowWords r;
+#pragma unroll
+    for (int q = 0; q < kRowHold; ++q) {
+        const uint32_t e = threadIdx.x + (uint32_t)q * blockDim.x;
+        r.w[q] = e < (uint32_t)kRowWords ? rows[(size_t)slot * kRowWords + e] : 0u;
+    }
+    return r;
+}
+
+__device__ __forceinline__ void put_rows(const RowWords &r, TileTables &tb)
+{
+#pragma unroll
+    for (int q = 0; q < kRowHold; ++q) {
+        const uint32_t e = threadIdx.x + (uint32_t)q * blockDim.x;
+        if (e < (uint32_t)kBndWords) (&tb.bnd[0][0])[e] = r.w[q];
+        else if (e < (uint32_t)kRowWords) tb.base[e - kBndWords] = r.w[q];
+    }
+}
+
+__device__ __forceinline__ bool stage_tables(const float4 *__restrict__ src, TileTables &tb,
+                                             float4 *__restrict__ stage)
+{
+    __syncthreads();
+    const bool fits = tb.base[kStageRows] <= (uint32_t)kStageCap;
+    if (fits) tile_stage(tb, src, stage);
+    return fits;
+}
+
 // Walk the neighbour list of particle p in stored order, calling f(position
 // and lambda of the neighbour); codes are read eight at a time.  FITS: every
 // code of a stored group is an LDS index (padding codes name the far-away
@@ -1550,13 +1591,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;
     if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[k + 1], slot)) return;  // active tiles
+    const RowWords row_w = saved_row_words(rows, slot);
     const uint4 rec = tile_rec[slot];  // tile, first p, own particles, scene
     const SceneDev &S = sc[rec.w];
     const uint32_t p0 = rec.y, nown = rec.z;
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
+    put_rows(row_w, tb);
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
-    if (!stage_rows(rows, slot, xs, tb, stage))
+    if (!stage_tables(xs, tb, stage))
         tile_lambda<false, !SPLIT, false>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
     else if (S.h <= 1.f)
         tile_lambda<true, !SPLIT, true>(k, S, tb, stage, xs, n, nbr, pmeta, pslot, p0, nown, first, last, hd);
@@ -1632,22 +1675,25 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     __shared__ float4 stage[kStageEntries];
     uint32_t slot;  // tiles with a particle of level >= k
     if (!xcd_slot(SPLIT ? blockIdx.x % tx : blockIdx.x, tile_ge[k > 1 ? k : 1], slot)) return;
+    const bool copy_only = slot >= tile_ge[k + 1];  // the tile's highest level is k
+    RowWords row_w{};
+    if (!copy_only) row_w = saved_row_words(rows, slot);
     const uint4 rec = tile_rec[slot];  // tile, first p, own particles, scene
     const SceneDev &S = sc[rec.w];
     const uint32_t p0 = rec.y, nown = rec.z;
     uint32_t first = 0, last = nown;
     if (SPLIT && !split_part(nown, blockIdx.x / tx, gridDim.x / tx, first, last)) return;
-    if (slot >= tile_ge[k + 1]) {
-        // the tile's highest level is k: its particles only copy across, so
-        // its neighbourhood is not staged
+    if (copy_only) {
+        // its particles only copy across, so its neighbourhood is not staged
         for (uint32_t pl = first + threadIdx.x; pl < last; pl += blockDim.x) {
             const uint32_t meta = pmeta[p0 + pl], i = pslot[p0 + pl];
             if ((int)meta_level(meta) == k) xs_out[i] = xs_in[i];
         }
         return;
     }
+    put_rows(row_w, tb);
     const Head hd = load_head(pmeta, pslot, nbr, p0, first, last);
-    if (!stage_rows(rows, slot, xs_in, tb, stage))
+    if (!stage_tables(xs_in, tb, stage))
         tile_update<false, CONTACTS, false>(k, S, tb, stage, xs_in, xs_out, n, nbr, pmeta, pslot, contact,
                                             p0, nown, first, last, hd);
     else if (S.h <= 1.f)
