@@ -283,6 +283,9 @@ SHAPES = [
     {"neighbours": 384, "lambda": 256, "update": 384, "lod_predict": 128, "sort_finish": 1024,
      "tile_prepare": 64, "commit": 512},
     {"neighbours": 128, "lambda": 128, "update": 128, "sort_scatter": 1024, "contacts": 1024},
+    # the smallest solver workgroups: each thread carries five words of the
+    # tile's saved stage tables
+    {"lambda": 64, "update": 64},
 ]
 
 
