@@ -333,6 +333,18 @@ pbf_status pbf_debug_levels(pbf_ctx *ctx, uint8_t *levels);
 /* Contacts found in the last step (bit o set: obstacle o of the particle's
  * scene); zeros where no scene has obstacles. */
 pbf_status pbf_debug_contacts(pbf_ctx *ctx, uint8_t *mask);
+/* Debug poisoning (enable 0 or 1): from the next step on, every step first
+ * fills the float buffers it writes before reading them (the predicted
+ * positions, both x* buffers with their lambda lanes, and the free halves of
+ * the position and velocity buffers) with quiet NaNs; the scene-index lane
+ * of the position buffer gets scene 0, so a stray read yields a NaN position,
+ * never an out-of-range scene.  A correct step is bit-identical with and
+ * without it; a read of a value the step did not write surfaces as
+ * PBF_ERR_NONFINITE from the commit's check or as NaN results.  Integer
+ * buffers (indices, codes, tables) are not poisoned, since a stray index
+ * would address memory out of bounds.  Changing it drops the captured step
+ * graphs.  Costs five fills of n float4 per step. */
+pbf_status pbf_debug_poison(pbf_ctx *ctx, int32_t enable);
 /* Save / restore the dynamic state (positions and velocities, ID order,
  * host buffers float[3 * n_total] each, plus the step counter).  A restored
  * context continues bit-identically to one that never stopped. */

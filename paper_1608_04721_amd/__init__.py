@@ -311,6 +311,11 @@ class Sim:
         self._check(self._lib.pbf_debug_contacts(self._ctx, out.ctypes.data), "pbf_debug_contacts")
         return out
 
+    def debug_poison(self, enable: bool = True):
+        """Fill the float buffers each step writes before reading them with
+        NaNs first (a debug check; results are unchanged when it passes)."""
+        self._check(self._lib.pbf_debug_poison(self._ctx, int(bool(enable))), "pbf_debug_poison")
+
     def debug_levels(self) -> np.ndarray:
         out = np.empty(self.n, np.uint8)
         self._check(self._lib.pbf_debug_levels(self._ctx, out.ctypes.data), "pbf_debug_levels")

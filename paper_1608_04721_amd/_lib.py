@@ -108,6 +108,7 @@ SIGNATURES = {
     "pbf_debug_lambda": (c_i32, [CTX, c_vp]),
     "pbf_debug_levels": (c_i32, [CTX, c_vp]),
     "pbf_debug_contacts": (c_i32, [CTX, c_vp]),
+    "pbf_debug_poison": (c_i32, [CTX, c_i32]),
     "pbf_get_state": (c_i32, [CTX, c_vp, c_vp, P(c_i64)]),
     "pbf_set_state": (c_i32, [CTX, c_vp, c_vp, c_i64]),
     "pbf_density": (c_i32, [CTX, c_vp, c_vp, c_i32]),

@@ -1339,6 +1339,19 @@ pbf_status pbf_debug_contacts(pbf_ctx *c, uint8_t *mask)
     return PBF_OK;
 }
 
+pbf_status pbf_debug_poison(pbf_ctx *c, int32_t enable)
+{
+    if (!c) return PBF_ERR_INVALID_ARG;
+    if (enable != 0 && enable != 1) return fail(c, PBF_ERR_INVALID_ARG, "enable must be 0 or 1");
+    const bool on = enable != 0;
+    if (on != c->b.poison) {
+        HIPCHK(c, hipStreamSynchronize(c->stream), "stream synchronize");
+        drop_graphs(c);  // the step's launches change
+    }
+    c->b.poison = on;
+    return PBF_OK;
+}
+
 pbf_status pbf_get_state(pbf_ctx *c, float *x, float *v, int64_t *step)
 {
     if (!c || ((!x || !v) && c->n_total)) return PBF_ERR_INVALID_ARG;

@@ -207,6 +207,7 @@ struct StepBuffers {
     uint8_t *contact;        // [n] contacts found this step, slot order (bit o: obstacle o)
     bool contacts_on;        // some scene has obstacles or pre-stabilisation
     bool cohesion_on;        // some scene has force-based cohesion
+    bool poison;             // debug: NaN-fill the float buffers each step writes before it reads them
     uint32_t *range;         // automatic distance ranges (min, max float bits per camera)
     uint32_t n_range;        // their words (0: no scene with an automatic range)
 };

@@ -28,6 +28,9 @@
 // atomics only count cell occupancy, and the resulting tickets are replaced
 // by the rank of the particle ID inside its cell.
 #include "pbf_internal.h"
+
+#include <algorithm>
+#include <limits>
 #include "../../include/pbf.h"
 
 namespace pbf {
@@ -1984,6 +1987,32 @@ inline unsigned blocks_for(int64_t n, int block)
         if (e_ != hipSuccess) return e_;                                        \
     } while (0)
 
+// Debug fill of one float4 buffer (a kernel, not a memset, so that a
+// captured step replays it like its other launches).
+__global__ void k_poison(int64_t n, float4 *__restrict__ p, float4 v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static hipError_t enqueue_poison(const StepBuffers &b, int nxt, hipStream_t s)
+{
+    // quiet NaN in every float; x.w holds the scene index, so the free
+    // position buffer gets scene 0 there: a stray read then gives a NaN
+    // position and never an out-of-range scene
+    const float qn = std::numeric_limits<float>::quiet_NaN();
+    const float4 all = make_float4(qn, qn, qn, qn), pos = make_float4(qn, qn, qn, 0.f);  // 0.f: all bits 0
+    const int64_t n = b.n;
+    const unsigned grid = (unsigned)std::min<int64_t>(blocks_for(n, 256), 4096);
+    float4 *const fill[] = {b.xs_pred, b.xs[0], b.xs[1], b.v[nxt]};
+    for (float4 *p : fill) {
+        hipLaunchKernelGGL(k_poison, dim3(grid), dim3(256), 0, s, n, p, all);
+        if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_poison, dim3(grid), dim3(256), 0, s, n, b.x[nxt], pos);
+    return hipGetLastError();
+}
+
 static hipError_t enqueue_scan(uint32_t *in, uint32_t count, uint32_t *part, uint32_t *out,
                                bool clear_in, hipStream_t s, Timer *tm)
 {
@@ -2023,6 +2052,7 @@ hipError_t enqueue_step(const StepBuffers &b0, int cur, const LaunchShape &ls, h
     const int *bs = ls.block;
     hipError_t e;
 
+    if (b.poison && (e = enqueue_poison(b, nxt, s)) != hipSuccess) return e;
     if (b.n_depth) {  // depth images of the distance-to-the-visible-surface scenes
         LAUNCH(K_DEPTH, blocks_for(b.n_depth, 256), 256, k_depth_clear, b.n_depth, b.depth);
         LAUNCH(K_DEPTH, blocks_for(n, kSplatThreads), kSplatThreads, k_depth_splat, n, b.scenes, b.x[cur],
